@@ -1,0 +1,583 @@
+// C ABI of the mortar library (declared in include/mortar.h): descriptor validation,
+// FP64 basis constants, device buffers, per-stage updates and kernel dispatch.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "k_flux.h"
+#include "mortar_internal.h"
+
+namespace mortar {
+hipError_t launch_flux_f32(const FluxArgs<float> &a, int NP, int grid, bool ns, bool met,
+                           int riem, hipStream_t st);
+hipError_t launch_flux_f64(const FluxArgs<double> &a, int NP, int grid, bool ns, bool met,
+                           int riem, hipStream_t st);
+int flux_tile_faces_f32(int NP, bool ns, bool met);
+int flux_tile_faces_f64(int NP, bool ns, bool met);
+
+// ------------------------------------------------------------------------------------
+// FP64 node sets by bracketing and bisection (roots of P_NP for Gauss, of P_N' for
+// Gauss-Lobatto), weights from the Legendre polynomials.
+// ------------------------------------------------------------------------------------
+
+// Legendre P_k(x) for k = n and n - 1 by the three-term recurrence.
+static void legendre_pair(int n, double x, double &pn, double &pn1)
+{
+    double a = 1.0, b = x;  // P_0, P_1
+    if (n == 0) { pn = 1.0; pn1 = 0.0; return; }
+    for (int k = 2; k <= n; ++k) {
+        const double c = ((2 * k - 1) * x * b - (k - 1) * a) / k;
+        a = b;
+        b = c;
+    }
+    pn = b;
+    pn1 = a;
+}
+
+// (1 - x^2) P_n'(x) = n (P_{n-1} - x P_n): sign-equivalent to P_n' inside (-1, 1).
+static double dlegendre_scaled(int n, double x)
+{
+    double pn, pn1;
+    legendre_pair(n, x, pn, pn1);
+    return n * (pn1 - x * pn);
+}
+
+template <typename Fn>
+static std::vector<double> interior_roots(Fn f, int count)
+{
+    // Sign changes on a uniform grid bracket the simple roots; a root that falls exactly
+    // on a grid point is taken as is and not bracketed again from its right.
+    std::vector<double> roots;
+    const int M = 4000;
+    const double lo0 = -1.0 + 1e-12, span = 2.0 - 2e-12;
+    double xa = lo0, fa = f(xa);
+    for (int i = 1; i <= M && (int)roots.size() < count; ++i) {
+        const double xb = lo0 + span * i / M, fb = f(xb);
+        if (fb == 0.0) {
+            roots.push_back(xb);
+        } else if (fa != 0.0 && ((fa < 0.0) != (fb < 0.0))) {
+            double lo = xa, hi = xb, flo = fa;
+            for (int it = 0; it < 200; ++it) {
+                const double mid = 0.5 * (lo + hi);
+                if (mid == lo || mid == hi) break;
+                const double fm = f(mid);
+                if (fm == 0.0) { lo = hi = mid; break; }
+                if ((fm < 0.0) == (flo < 0.0)) { lo = mid; flo = fm; } else hi = mid;
+            }
+            roots.push_back(0.5 * (lo + hi));
+        }
+        xa = xb;
+        fa = fb;
+    }
+    return roots;
+}
+
+static bool gauss_nodes(int np, double *x, double *w)
+{
+    auto f = [np](double t) { double a, b; legendre_pair(np, t, a, b); return a; };
+    std::vector<double> r = interior_roots(f, np);
+    if ((int)r.size() != np) return false;
+    for (int i = 0; i < np; ++i) {
+        x[i] = r[i];
+        // w = 2 (1 - x^2) / (n P_{n-1}(x))^2  for roots of P_n
+        double pn, pn1;
+        legendre_pair(np, r[i], pn, pn1);
+        w[i] = 2.0 * (1.0 - r[i] * r[i]) / ((np * pn1) * (np * pn1));
+    }
+    return true;
+}
+
+static bool lobatto_nodes(int N, double *x, double *w)
+{
+    auto f = [N](double t) { return dlegendre_scaled(N, t); };
+    std::vector<double> r = interior_roots(f, N - 1);
+    if ((int)r.size() != N - 1) return false;
+    x[0] = -1.0;
+    x[N] = 1.0;
+    for (int i = 0; i < N - 1; ++i) x[i + 1] = r[i];
+    for (int i = 0; i <= N; ++i) {
+        double pn, pn1;
+        legendre_pair(N, x[i], pn, pn1);
+        w[i] = 2.0 / (N * (N + 1.0) * pn * pn);
+    }
+    return true;
+}
+
+static double lagrange_bary(int np, const double *x, const double *bw, int j, double t)
+{
+    for (int m = 0; m < np; ++m)
+        if (t == x[m]) return m == j ? 1.0 : 0.0;
+    double den = 0.0;
+    for (int m = 0; m < np; ++m) den += bw[m] / (t - x[m]);
+    return bw[j] / (t - x[j]) / den;
+}
+
+static bool invert_gj(int n, const double *A, double *R, int ld)
+{
+    double a[kMaxNP][2 * kMaxNP];
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            a[i][j] = A[i * n + j];
+            a[i][n + j] = i == j;
+        }
+    for (int c = 0; c < n; ++c) {
+        int p = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(a[r][c]) > std::fabs(a[p][c])) p = r;
+        if (a[p][c] == 0.0) return false;
+        for (int j = 0; j < 2 * n; ++j) std::swap(a[c][j], a[p][j]);
+        const double d = 1.0 / a[c][c];
+        for (int j = 0; j < 2 * n; ++j) a[c][j] *= d;
+        for (int r = 0; r < n; ++r)
+            if (r != c) {
+                const double g = a[r][c];
+                for (int j = 0; j < 2 * n; ++j) a[r][j] -= g * a[c][j];
+            }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) R[i * ld + j] = a[i][n + j];
+    return true;
+}
+
+static bool basis_consts(int N, int node_set, BasisConsts &c)
+{
+    std::memset(&c, 0, sizeof(c));
+    const int np = N + 1;
+    const bool ok = node_set == MORTAR_NODES_GAUSS ? gauss_nodes(np, c.x, c.w)
+                                                   : lobatto_nodes(N, c.x, c.w);
+    if (!ok || !gauss_nodes(np, c.t, c.tw)) return false;
+    for (int j = 0; j < np; ++j) {
+        double p = 1.0;
+        for (int m = 0; m < np; ++m)
+            if (m != j) p *= c.x[j] - c.x[m];
+        c.bw[j] = 1.0 / p;
+    }
+    for (int r = 0; r < np; ++r)
+        for (int q = 0; q < np; ++q) c.Lt[r * kMaxNP + q] = lagrange_bary(np, c.x, c.bw, q, c.t[r]);
+    // mass matrix M_ij = int l_i l_j with the np-point Gauss rule (exact to degree 2N+1)
+    double M[kMaxNP * kMaxNP];
+    for (int i = 0; i < np; ++i)
+        for (int j = 0; j < np; ++j) {
+            double acc = 0.0;
+            for (int r = 0; r < np; ++r) acc += c.tw[r] * c.Lt[r * kMaxNP + i] * c.Lt[r * kMaxNP + j];
+            M[i * np + j] = acc;
+        }
+    return invert_gj(np, M, c.Minv, kMaxNP);
+}
+
+// ------------------------------------------------------------------------------------
+
+static int validate_one(const mortar_iface_desc &d)
+{
+    if (d.N < 1 || d.n_par < 1 || d.n_perp < 1) return MORTAR_ERR_INVALID_ARG;
+    if (d.N > kMaxN) return MORTAR_ERR_UNSUPPORTED;
+    if (d.node_set != MORTAR_NODES_GAUSS && d.node_set != MORTAR_NODES_LGL)
+        return MORTAR_ERR_INVALID_ARG;
+    if (d.physics != MORTAR_EULER && d.physics != MORTAR_NAVIER_STOKES) return MORTAR_ERR_INVALID_ARG;
+    if (d.riemann != MORTAR_FLUX_LF && d.riemann != MORTAR_FLUX_ROE) return MORTAR_ERR_INVALID_ARG;
+    if (d.precision < MORTAR_FP64 || d.precision > MORTAR_FP16_MFMA) return MORTAR_ERR_INVALID_ARG;
+    if (d.precision == MORTAR_BF16_MFMA || d.precision == MORTAR_FP16_MFMA)
+        return MORTAR_ERR_UNSUPPORTED;
+    const int64_t F = (int64_t)d.n_par * d.n_perp;
+    if (F > (int64_t)1 << 28) return MORTAR_ERR_UNSUPPORTED;
+    if (d.n_face_static < F || d.n_face_moving < F) return MORTAR_ERR_INVALID_ARG;
+    const int64_t P = (int64_t)(d.N + 1) * (d.N + 1);
+    if (P * 20 * (int64_t)std::max(d.n_face_static, d.n_face_moving) > ((int64_t)1 << 40))
+        return MORTAR_ERR_UNSUPPORTED;
+    if (!d.face_id_static || !d.face_id_moving) return MORTAR_ERR_INVALID_ARG;
+    if (!(std::isfinite(d.l_par) && d.l_par > 0.0)) return MORTAR_ERR_INVALID_ARG;
+    if (!(std::isfinite(d.gamma) && d.gamma > 1.0)) return MORTAR_ERR_INVALID_ARG;
+    if (d.physics == MORTAR_NAVIER_STOKES &&
+        !(std::isfinite(d.mu) && d.mu >= 0.0 && std::isfinite(d.Pr) && d.Pr > 0.0))
+        return MORTAR_ERR_INVALID_ARG;
+    if (!d.metrics) {
+        const double nn = d.normal[0] * d.normal[0] + d.normal[1] * d.normal[1] +
+                          d.normal[2] * d.normal[2];
+        if (!(std::isfinite(nn) && std::fabs(nn - 1.0) < 1e-6 && std::isfinite(d.dS)))
+            return MORTAR_ERR_INVALID_ARG;
+    }
+    // face ids: in range and distinct per side
+    for (int side = 0; side < 2; ++side) {
+        const int32_t *fid = side ? d.face_id_moving : d.face_id_static;
+        const int nf = side ? d.n_face_moving : d.n_face_static;
+        std::vector<char> seen(nf, 0);
+        for (int64_t i = 0; i < F; ++i) {
+            const int32_t c = fid[i];
+            if (c < 0 || c >= nf || seen[c]) return MORTAR_ERR_INVALID_ARG;
+            seen[c] = 1;
+        }
+        const int32_t *own = side ? d.owner_moving : d.owner_static;
+        if (own) {
+            std::vector<int32_t> u(own, own + F);
+            std::sort(u.begin(), u.end());
+            if (std::unique(u.begin(), u.end()) - u.begin() > kMaxOwners) return MORTAR_ERR_UNSUPPORTED;
+        }
+    }
+    return MORTAR_OK;
+}
+
+static void free_iface(Iface &f)
+{
+    void *bufs[] = {f.d_fid_s, f.d_fid_m, f.d_oid_s, f.d_oid_m, f.d_oval_s, f.d_oval_m,
+                    f.d_metrics, f.d_params, f.d_basis, f.d_A[0], f.d_A[1], f.d_m[0],
+                    f.d_m[1], f.d_hist, f.d_cons};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    f = Iface();
+}
+
+#define TRY_HIP(x)                                   \
+    do {                                             \
+        if ((x) != hipSuccess) return MORTAR_ERR_HIP; \
+    } while (0)
+
+template <typename T>
+static int upload(T **dst, const T *src, size_t count)
+{
+    if (hipMalloc((void **)dst, sizeof(T) * std::max<size_t>(count, 1)) != hipSuccess)
+        return MORTAR_ERR_OOM;
+    if (count) TRY_HIP(hipMemcpy(*dst, src, sizeof(T) * count, hipMemcpyHostToDevice));
+    return MORTAR_OK;
+}
+
+// Dense owner ids (ascending owner value) of one side.
+static void owner_ids(const int32_t *own, int64_t F, std::vector<int32_t> &ids,
+                      std::vector<int32_t> &vals)
+{
+    ids.assign(F, 0);
+    vals.assign(1, 0);
+    if (!own) return;
+    vals.assign(own, own + F);
+    std::sort(vals.begin(), vals.end());
+    vals.erase(std::unique(vals.begin(), vals.end()), vals.end());
+    for (int64_t i = 0; i < F; ++i)
+        ids[i] = (int32_t)(std::lower_bound(vals.begin(), vals.end(), own[i]) - vals.begin());
+}
+
+static int setup_one(const mortar_iface_desc &d, Iface &f)
+{
+    f.d = d;
+    f.d.face_id_static = f.d.face_id_moving = nullptr;
+    f.d.owner_static = f.d.owner_moving = nullptr;
+    f.d.metrics = nullptr;
+    f.NP = d.N + 1;
+    f.P = f.NP * f.NP;
+    f.F = d.n_par * d.n_perp;
+    f.elem = d.precision == MORTAR_FP64 ? 8 : 4;
+    int rc;
+    if ((rc = upload(&f.d_fid_s, d.face_id_static, f.F))) return rc;
+    if ((rc = upload(&f.d_fid_m, d.face_id_moving, f.F))) return rc;
+    std::vector<int32_t> ids, vals;
+    owner_ids(d.owner_static, f.F, ids, vals);
+    f.R_s = (int)vals.size();
+    if ((rc = upload(&f.d_oid_s, ids.data(), ids.size()))) return rc;
+    if ((rc = upload(&f.d_oval_s, vals.data(), vals.size()))) return rc;
+    owner_ids(d.owner_moving, f.F, ids, vals);
+    f.R_m = (int)vals.size();
+    if ((rc = upload(&f.d_oid_m, ids.data(), ids.size()))) return rc;
+    if ((rc = upload(&f.d_oval_m, vals.data(), vals.size()))) return rc;
+    if (d.metrics) {
+        const size_t cnt = (size_t)4 * f.P * d.n_face_static;
+        if (f.elem == 8) {
+            double *p;
+            if ((rc = upload(&p, d.metrics, cnt))) return rc;
+            f.d_metrics = p;
+        } else {
+            std::vector<float> tmp(d.metrics, d.metrics + cnt);
+            float *p;
+            if ((rc = upload(&p, tmp.data(), cnt))) return rc;
+            f.d_metrics = p;
+        }
+    }
+    BasisConsts bc;
+    if (!basis_consts(d.N, d.node_set, bc)) return MORTAR_ERR_UNSUPPORTED;
+    if ((rc = upload(&f.d_basis, &bc, 1))) return rc;
+    if (hipMalloc((void **)&f.d_params, param_bytes(f.NP)) != hipSuccess) return MORTAR_ERR_OOM;
+    TRY_HIP(hipMemset(f.d_params, 0, param_bytes(f.NP)));
+    for (int s = 0; s < 2; ++s) {
+        const int nf = s ? d.n_face_moving : d.n_face_static;
+        if (hipMalloc((void **)&f.d_A[s], sizeof(int32_t) * 5 * 2 * (size_t)f.F) != hipSuccess ||
+            hipMalloc((void **)&f.d_m[s], sizeof(int32_t) * 2 * (size_t)nf) != hipSuccess)
+            return MORTAR_ERR_OOM;
+    }
+    f.n_sort_blocks = (2 * f.F + kSortBlock - 1) / kSortBlock;
+    const int R = std::max(f.R_s, f.R_m);
+    if (hipMalloc((void **)&f.d_hist, sizeof(int32_t) * (size_t)R * f.n_sort_blocks) != hipSuccess)
+        return MORTAR_ERR_OOM;
+    f.n_cons_blocks = std::min(256, std::max(1, (f.F + 255) / 256));
+    if (hipMalloc((void **)&f.d_cons, sizeof(double) * 30 * (size_t)f.n_cons_blocks) != hipSuccess)
+        return MORTAR_ERR_OOM;
+    return MORTAR_OK;
+}
+
+// R6 of the design notes: FP64, no contraction, s in [0, 1).
+static void decompose(double delta, double l, int64_t &n, double &s)
+{
+    const double q = delta / l;
+    const double fl = std::floor(q);
+    double frac = q - fl;
+    int64_t k = (int64_t)fl;
+    if (frac >= 1.0) {
+        frac -= 1.0;
+        k += 1;
+    }
+    if (!(frac > 0.0)) frac = 0.0;
+    n = k;
+    s = frac;
+}
+
+static int apply_update(Handle *h, const int64_t *n, const double *s, hipStream_t st)
+{
+    for (auto &f : h->ifs) {
+        const size_t i = &f - h->ifs.data();
+        f.n = n[i];
+        f.s = s[i];
+        const int64_t np = f.d.n_par;
+        const int64_t nmod = ((f.n % np) + np) % np;
+        if (nmod != f.nmod_built) {
+            TRY_HIP(launch_index_map(f, 0, st));
+            TRY_HIP(launch_index_map(f, 1, st));
+            f.nmod_built = nmod;
+        }
+        TRY_HIP(launch_assemble(f, st));
+        f.ready = true;
+    }
+    return MORTAR_OK;
+}
+
+}  // namespace mortar
+
+using namespace mortar;
+
+struct mortar_handle : public mortar::Handle {};
+
+extern "C" {
+
+const char *mortar_error_string(int code)
+{
+    switch (code) {
+    case MORTAR_OK: return "ok";
+    case MORTAR_ERR_INVALID_ARG: return "invalid argument";
+    case MORTAR_ERR_UNSUPPORTED: return "unsupported configuration";
+    case MORTAR_ERR_OOM: return "out of memory";
+    case MORTAR_ERR_HIP: return "HIP runtime error";
+    case MORTAR_ERR_NOT_READY: return "no displacement set yet";
+    default: return "unknown error";
+    }
+}
+
+int mortar_validate(const mortar_iface_desc *desc, int n_iface)
+{
+    if (!desc || n_iface < 1) return MORTAR_ERR_INVALID_ARG;
+    for (int i = 0; i < n_iface; ++i) {
+        const int rc = validate_one(desc[i]);
+        if (rc) return rc;
+    }
+    return MORTAR_OK;
+}
+
+int mortar_basis(int N, int node_set, double *x, double *w)
+{
+    if (!x || !w || N < 1) return MORTAR_ERR_INVALID_ARG;
+    if (N > kMaxN) return MORTAR_ERR_UNSUPPORTED;
+    if (node_set != MORTAR_NODES_GAUSS && node_set != MORTAR_NODES_LGL) return MORTAR_ERR_INVALID_ARG;
+    BasisConsts c;
+    if (!basis_consts(N, node_set, c)) return MORTAR_ERR_UNSUPPORTED;
+    for (int i = 0; i <= N; ++i) {
+        x[i] = c.x[i];
+        w[i] = c.w[i];
+    }
+    return MORTAR_OK;
+}
+
+int mortar_decompose_displacement(double delta, double l_par, int64_t *n, double *s)
+{
+    if (!n || !s || !std::isfinite(delta) || !(std::isfinite(l_par) && l_par > 0.0))
+        return MORTAR_ERR_INVALID_ARG;
+    const double q = delta / l_par;
+    if (!(std::fabs(q) < 9.0e15)) return MORTAR_ERR_INVALID_ARG;
+    decompose(delta, l_par, *n, *s);
+    return MORTAR_OK;
+}
+
+int mortar_setup(const mortar_iface_desc *desc, int n_iface, mortar_handle **out)
+{
+    if (!out) return MORTAR_ERR_INVALID_ARG;
+    int rc = mortar_validate(desc, n_iface);
+    if (rc) return rc;
+    mortar_handle *h = new (std::nothrow) mortar_handle();
+    if (!h) return MORTAR_ERR_OOM;
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        return MORTAR_ERR_HIP;
+    }
+    h->ifs.resize(n_iface);
+    for (int i = 0; i < n_iface; ++i) {
+        rc = setup_one(desc[i], h->ifs[i]);
+        if (rc) {
+            for (auto &f : h->ifs) free_iface(f);
+            delete h;
+            return rc;
+        }
+    }
+    *out = h;
+    return MORTAR_OK;
+}
+
+int mortar_destroy(mortar_handle *h)
+{
+    if (!h) return MORTAR_ERR_INVALID_ARG;
+    (void)hipDeviceSynchronize();
+    for (auto &f : h->ifs) free_iface(f);
+    delete h;
+    return MORTAR_OK;
+}
+
+int mortar_update_displacement(mortar_handle *h, const double *disp, void *stream)
+{
+    if (!h || !disp) return MORTAR_ERR_INVALID_ARG;
+    const size_t n_if = h->ifs.size();
+    std::vector<int64_t> n(n_if);
+    std::vector<double> s(n_if);
+    for (size_t i = 0; i < n_if; ++i) {
+        const int rc = mortar_decompose_displacement(disp[i], h->ifs[i].d.l_par, &n[i], &s[i]);
+        if (rc) return rc;
+    }
+    return apply_update(h, n.data(), s.data(), (hipStream_t)stream);
+}
+
+int mortar_update_displacement_ns(mortar_handle *h, const int64_t *n, const double *s,
+                                  void *stream)
+{
+    if (!h || !n || !s) return MORTAR_ERR_INVALID_ARG;
+    for (size_t i = 0; i < h->ifs.size(); ++i)
+        if (!(s[i] >= 0.0 && s[i] < 1.0)) return MORTAR_ERR_INVALID_ARG;
+    return apply_update(h, n, s, (hipStream_t)stream);
+}
+
+int mortar_flux(mortar_handle *h, const void *const *U_s, const void *const *U_m,
+                const void *const *G_s, const void *const *G_m, void *const *F_s,
+                void *const *F_m, void *stream)
+{
+    if (!h || !U_s || !U_m || !F_s || !F_m) return MORTAR_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    for (size_t i = 0; i < h->ifs.size(); ++i) {
+        const Iface &f = h->ifs[i];
+        if (!f.ready) return MORTAR_ERR_NOT_READY;
+        const bool ns = f.d.physics == MORTAR_NAVIER_STOKES;
+        if (!U_s[i] || !U_m[i] || !F_s[i] || !F_m[i]) return MORTAR_ERR_INVALID_ARG;
+        if (ns && (!G_s || !G_m || !G_s[i] || !G_m[i])) return MORTAR_ERR_INVALID_ARG;
+        TRY_HIP(launch_flux(f, U_s[i], U_m[i], ns ? G_s[i] : nullptr, ns ? G_m[i] : nullptr,
+                            F_s[i], F_m[i], st));
+    }
+    return MORTAR_OK;
+}
+
+int mortar_get_displacement(mortar_handle *h, int iface, int64_t *n, double *s)
+{
+    if (!h || iface < 0 || iface >= (int)h->ifs.size() || !n || !s) return MORTAR_ERR_INVALID_ARG;
+    if (!h->ifs[iface].ready) return MORTAR_ERR_NOT_READY;
+    *n = h->ifs[iface].n;
+    *s = h->ifs[iface].s;
+    return MORTAR_OK;
+}
+
+int mortar_get_index_map(mortar_handle *h, int iface, int side, int32_t *A, int32_t *m)
+{
+    if (!h || iface < 0 || iface >= (int)h->ifs.size() || side < 0 || side > 1)
+        return MORTAR_ERR_INVALID_ARG;
+    const Iface &f = h->ifs[iface];
+    if (!f.ready) return MORTAR_ERR_NOT_READY;
+    TRY_HIP(hipDeviceSynchronize());
+    if (A) TRY_HIP(hipMemcpy(A, f.d_A[side], sizeof(int32_t) * 10 * (size_t)f.F, hipMemcpyDeviceToHost));
+    const int nf = side ? f.d.n_face_moving : f.d.n_face_static;
+    if (m) TRY_HIP(hipMemcpy(m, f.d_m[side], sizeof(int32_t) * 2 * (size_t)nf, hipMemcpyDeviceToHost));
+    return MORTAR_OK;
+}
+
+int mortar_get_projection(mortar_handle *h, int iface, double *Pf, double *Pb)
+{
+    if (!h || iface < 0 || iface >= (int)h->ifs.size()) return MORTAR_ERR_INVALID_ARG;
+    const Iface &f = h->ifs[iface];
+    if (!f.ready) return MORTAR_ERR_NOT_READY;
+    TRY_HIP(hipDeviceSynchronize());
+    const size_t nn = (size_t)4 * f.NP * f.NP;
+    if (Pf) TRY_HIP(hipMemcpy(Pf, f.d_params + off_f64(f.NP), sizeof(double) * nn, hipMemcpyDeviceToHost));
+    if (Pb)
+        TRY_HIP(hipMemcpy(Pb, f.d_params + off_f64(f.NP) + sizeof(double) * nn, sizeof(double) * nn,
+                          hipMemcpyDeviceToHost));
+    return MORTAR_OK;
+}
+
+int mortar_conservation(mortar_handle *h, const void *const *F_s, const void *const *F_m,
+                        double *out, void *stream)
+{
+    if (!h || !F_s || !F_m || !out) return MORTAR_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t n_if = h->ifs.size();
+    double *d_out = nullptr;
+    if (hipMalloc((void **)&d_out, sizeof(double) * 15 * n_if) != hipSuccess) return MORTAR_ERR_OOM;
+    int rc = MORTAR_OK;
+    for (size_t i = 0; i < n_if && rc == MORTAR_OK; ++i) {
+        if (!F_s[i] || !F_m[i]) rc = MORTAR_ERR_INVALID_ARG;
+        else if (launch_conservation(h->ifs[i], F_s[i], F_m[i], d_out + 15 * i, st) != hipSuccess)
+            rc = MORTAR_ERR_HIP;
+    }
+    if (rc == MORTAR_OK) {
+        if (hipMemcpyAsync(out, d_out, sizeof(double) * 15 * n_if, hipMemcpyDeviceToHost, st) !=
+                hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            rc = MORTAR_ERR_HIP;
+    }
+    (void)hipFree(d_out);
+    return rc;
+}
+
+}  // extern "C"
+
+namespace mortar {
+
+hipError_t launch_flux(const Iface &f, const void *Us, const void *Um, const void *Gs,
+                       const void *Gm, void *Fs, void *Fm, hipStream_t st)
+{
+    const bool ns = f.d.physics == MORTAR_NAVIER_STOKES;
+    const bool met = f.d_metrics != nullptr;
+    const int riem = f.d.riemann == MORTAR_FLUX_ROE ? 1 : 0;
+    const double gm1 = f.d.gamma - 1.0;
+    const double kfac = ns ? f.d.mu * f.d.gamma / (gm1 * f.d.Pr) : 0.0;
+    if (f.elem == 8) {
+        FluxArgs<double> a;
+        a.Us = (const double *)Us; a.Um = (const double *)Um;
+        a.Gs = (const double *)Gs; a.Gm = (const double *)Gm;
+        a.met = (const double *)f.d_metrics;
+        a.Fs = (double *)Fs; a.Fm = (double *)Fm;
+        a.fid_s = f.d_fid_s; a.fid_m = f.d_fid_m; a.params = f.d_params;
+        a.n_par = f.d.n_par; a.n_perp = f.d.n_perp;
+        a.nfs = f.d.n_face_static; a.nfm = f.d.n_face_moving;
+        const int tf = flux_tile_faces_f64(f.NP, ns, met);
+        a.tiles_per_row = (f.d.n_par + tf - 1) / tf;
+        a.nx = f.d.normal[0]; a.ny = f.d.normal[1]; a.nz = f.d.normal[2]; a.dS = f.d.dS;
+        a.gas = {gm1, f.d.gamma, ns ? f.d.mu : 0.0, kfac};
+        const int grid = a.tiles_per_row * f.NP * f.d.n_perp;
+        return launch_flux_f64(a, f.NP, grid, ns, met, riem, st);
+    }
+    FluxArgs<float> a;
+    a.Us = (const float *)Us; a.Um = (const float *)Um;
+    a.Gs = (const float *)Gs; a.Gm = (const float *)Gm;
+    a.met = (const float *)f.d_metrics;
+    a.Fs = (float *)Fs; a.Fm = (float *)Fm;
+    a.fid_s = f.d_fid_s; a.fid_m = f.d_fid_m; a.params = f.d_params;
+    a.n_par = f.d.n_par; a.n_perp = f.d.n_perp;
+    a.nfs = f.d.n_face_static; a.nfm = f.d.n_face_moving;
+    const int tf = flux_tile_faces_f32(f.NP, ns, met);
+    a.tiles_per_row = (f.d.n_par + tf - 1) / tf;
+    a.nx = (float)f.d.normal[0]; a.ny = (float)f.d.normal[1]; a.nz = (float)f.d.normal[2];
+    a.dS = (float)f.d.dS;
+    a.gas = {(float)gm1, (float)f.d.gamma, (float)(ns ? f.d.mu : 0.0), (float)kfac};
+    const int grid = a.tiles_per_row * f.NP * f.d.n_perp;
+    return launch_flux_f32(a, f.NP, grid, ns, met, riem, st);
+}
+
+}  // namespace mortar

@@ -1,0 +1,87 @@
+// Internal declarations of the MI355X mortar library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "mortar.h"
+
+namespace mortar {
+
+constexpr int kMaxN = 9;
+constexpr int kMaxNP = kMaxN + 1;
+constexpr int kMaxOwners = 1024;   // distinct owner ranks per side (index-map sort keys)
+constexpr int kSortBlock = 256;    // elements per block of the index-map counting sort
+
+// Per-interface device parameter block, rewritten by the assembly kernel every stage.
+// Header followed by matrices: double Pf[4][NP][NP], double Pb[4][NP][NP],
+// float Pf[4][NP][NP], float Pb[4][NP][NP].  Matrix order k: static i_sub 0, static
+// i_sub 1, moving i_sub 0 (upper part of the moving face), moving i_sub 1 (lower part).
+struct alignas(16) ParamHeader {
+    int32_t nmod;  // n mod n_par
+    int32_t NP;
+    int64_t n;
+    double s;
+    double pad;
+};
+constexpr size_t kHeaderBytes = sizeof(ParamHeader);  // 32
+
+__host__ __device__ inline size_t param_bytes(int NP) {
+    // 8 matrices (4 forward, 4 backward) in double and again in float
+    return kHeaderBytes + (size_t)8 * NP * NP * (sizeof(double) + sizeof(float));
+}
+__host__ __device__ inline size_t off_f64(int) { return kHeaderBytes; }
+__host__ __device__ inline size_t off_f32(int NP) { return kHeaderBytes + (size_t)8 * NP * NP * sizeof(double); }
+
+// FP64 constants of one interface's basis, uploaded once at setup (Sec. 3.2: the mass
+// matrix depends only on the basis).
+struct BasisConsts {
+    double x[kMaxNP];                 // nodes
+    double w[kMaxNP];                 // quadrature weights of the nodes
+    double bw[kMaxNP];                // barycentric weights 1 / prod_{m != j} (x_j - x_m)
+    double t[kMaxNP];                 // Gauss rule used for S (exact for degree 2N)
+    double tw[kMaxNP];
+    double Lt[kMaxNP * kMaxNP];       // l_q(t_r), [r][q]
+    double Minv[kMaxNP * kMaxNP];     // inverse mass matrix
+};
+
+struct Iface {
+    mortar_iface_desc d{};
+    int NP = 0, P = 0, F = 0;          // points per direction, per face, face pairs
+    size_t elem = 8;                   // bytes per element of U/G/F
+    // device buffers
+    int32_t *d_fid_s = nullptr, *d_fid_m = nullptr;
+    int32_t *d_oid_s = nullptr, *d_oid_m = nullptr;  // dense owner ids [n_perp*n_par]
+    int32_t *d_oval_s = nullptr, *d_oval_m = nullptr; // owner value per dense id
+    int R_s = 1, R_m = 1;              // distinct owners per side
+    void *d_metrics = nullptr;         // [4][P][n_face_static] in element type, or null
+    char *d_params = nullptr;          // ParamHeader + matrices
+    BasisConsts *d_basis = nullptr;
+    int32_t *d_A[2] = {nullptr, nullptr};  // [5][2F] per side
+    int32_t *d_m[2] = {nullptr, nullptr};  // [2][n_face] per side
+    int32_t *d_hist = nullptr;             // [R][n_sort_blocks] counting-sort scratch
+    int n_sort_blocks = 0;
+    int64_t n = 0;
+    double s = 0.0;
+    int64_t nmod_built = -1;           // n mod n_par of the current index map
+    bool ready = false;
+    double *d_cons = nullptr;          // conservation partials
+    int n_cons_blocks = 0;
+};
+
+struct Handle {
+    int device = 0;
+    std::vector<Iface> ifs;
+};
+
+// ---- launchers (kernels in k_*.hip) ------------------------------------------------
+hipError_t launch_assemble(const Iface &f, hipStream_t st);
+hipError_t launch_index_map(Iface &f, int side, hipStream_t st);
+hipError_t launch_flux(const Iface &f, const void *Us, const void *Um, const void *Gs,
+                       const void *Gm, void *Fs, void *Fm, hipStream_t st);
+hipError_t launch_conservation(const Iface &f, const void *Fs, const void *Fm, double *d_out,
+                               hipStream_t st);
+
+}  // namespace mortar

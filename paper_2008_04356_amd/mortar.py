@@ -1,0 +1,252 @@
+"""Thin ctypes binding of libmortar.so (C ABI in include/mortar.h).
+
+Argument marshalling only: every step of the operator runs in the HIP library.  Torch
+is used for device memory and streams.  There is no fallback: if the library is missing
+or fails to load, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmortar.so")
+
+OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OOM, ERR_HIP, ERR_NOT_READY = 0, -1, -2, -3, -4, -5
+GEOM_PLANE, GEOM_ANNULUS = 0, 1
+NODES_GAUSS, NODES_LGL = 0, 1
+EULER, NAVIER_STOKES = 0, 1
+FLUX_LF, FLUX_ROE = 0, 1
+FP64, FP32, BF16_MFMA, FP16_MFMA = 0, 1, 2, 3
+
+_ip = C.POINTER(C.c_int32)
+_dp = C.POINTER(C.c_double)
+_vpp = C.POINTER(C.c_void_p)
+
+
+class mortar_iface_desc(C.Structure):
+    _fields_ = [
+        ("geometry", C.c_int32), ("N", C.c_int32), ("node_set", C.c_int32),
+        ("n_par", C.c_int32), ("n_perp", C.c_int32),
+        ("n_face_static", C.c_int32), ("n_face_moving", C.c_int32),
+        ("face_id_static", _ip), ("face_id_moving", _ip),
+        ("owner_static", _ip), ("owner_moving", _ip),
+        ("l_par", C.c_double), ("normal", C.c_double * 3), ("dS", C.c_double),
+        ("metrics", _dp),
+        ("physics", C.c_int32), ("riemann", C.c_int32), ("precision", C.c_int32),
+        ("reserved", C.c_int32),
+        ("gamma", C.c_double), ("mu", C.c_double), ("Pr", C.c_double),
+    ]
+
+
+class MortarError(RuntimeError):
+    pass
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2008_04356_amd/build.py "
+                          "(there is no CPU fallback)")
+    L = C.CDLL(LIB_PATH)
+    L.mortar_validate.argtypes = [C.POINTER(mortar_iface_desc), C.c_int]
+    L.mortar_setup.argtypes = [C.POINTER(mortar_iface_desc), C.c_int, C.POINTER(C.c_void_p)]
+    L.mortar_update_displacement.argtypes = [C.c_void_p, _dp, C.c_void_p]
+    L.mortar_update_displacement_ns.argtypes = [C.c_void_p, C.POINTER(C.c_int64), _dp, C.c_void_p]
+    L.mortar_flux.argtypes = [C.c_void_p, _vpp, _vpp, _vpp, _vpp, _vpp, _vpp, C.c_void_p]
+    L.mortar_destroy.argtypes = [C.c_void_p]
+    L.mortar_error_string.argtypes = [C.c_int]
+    L.mortar_error_string.restype = C.c_char_p
+    L.mortar_decompose_displacement.argtypes = [C.c_double, C.c_double, C.POINTER(C.c_int64), _dp]
+    L.mortar_basis.argtypes = [C.c_int, C.c_int, _dp, _dp]
+    L.mortar_get_displacement.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int64), _dp]
+    L.mortar_get_index_map.argtypes = [C.c_void_p, C.c_int, C.c_int, _ip, _ip]
+    L.mortar_get_projection.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
+    L.mortar_conservation.argtypes = [C.c_void_p, _vpp, _vpp, _dp, C.c_void_p]
+    return L
+
+
+lib = _load()
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        raise MortarError(f"{what}: {lib.mortar_error_string(rc).decode()} ({rc})")
+
+
+# ---- same names as the C ABI (argument marshalling only) -----------------------------
+
+def mortar_validate(descs) -> int:
+    arr = (mortar_iface_desc * len(descs))(*descs)
+    return lib.mortar_validate(arr, len(descs))
+
+
+def mortar_setup(descs) -> C.c_void_p:
+    arr = (mortar_iface_desc * len(descs))(*descs)
+    h = C.c_void_p()
+    _check(lib.mortar_setup(arr, len(descs), C.byref(h)), "mortar_setup")
+    return h
+
+
+def mortar_update_displacement(h, disp: Sequence[float], stream: int = 0) -> int:
+    d = (C.c_double * len(disp))(*[float(x) for x in disp])
+    return lib.mortar_update_displacement(h, d, C.c_void_p(stream))
+
+
+def mortar_update_displacement_ns(h, n: Sequence[int], s: Sequence[float], stream: int = 0) -> int:
+    nn = (C.c_int64 * len(n))(*[int(x) for x in n])
+    ss = (C.c_double * len(s))(*[float(x) for x in s])
+    return lib.mortar_update_displacement_ns(h, nn, ss, C.c_void_p(stream))
+
+
+def _ptrs(ts):
+    if ts is None:
+        return None
+    return (C.c_void_p * len(ts))(*[None if t is None else C.c_void_p(int(t)) for t in ts])
+
+
+def mortar_flux(h, Us, Um, Gs, Gm, Fs, Fm, stream: int = 0) -> int:
+    """Each argument: a sequence of device addresses (ints) or None entries."""
+    return lib.mortar_flux(h, _ptrs(Us), _ptrs(Um), _ptrs(Gs), _ptrs(Gm), _ptrs(Fs), _ptrs(Fm),
+                           C.c_void_p(stream))
+
+
+def mortar_destroy(h) -> int:
+    return lib.mortar_destroy(h)
+
+
+def mortar_error_string(code: int) -> str:
+    return lib.mortar_error_string(code).decode()
+
+
+def mortar_basis(N: int, node_set: int):
+    x = np.zeros(N + 1)
+    w = np.zeros(N + 1)
+    _check(lib.mortar_basis(N, node_set, x.ctypes.data_as(_dp), w.ctypes.data_as(_dp)), "mortar_basis")
+    return x, w
+
+
+def mortar_decompose_displacement(delta: float, l_par: float):
+    n = C.c_int64()
+    s = C.c_double()
+    _check(lib.mortar_decompose_displacement(delta, l_par, C.byref(n), C.byref(s)),
+           "mortar_decompose_displacement")
+    return int(n.value), float(s.value)
+
+
+# ---- descriptors from workload specs --------------------------------------------------
+
+class _Keep:
+    pass
+
+
+def make_desc(spec, keep: Optional[list] = None) -> mortar_iface_desc:
+    """Descriptor of a workloads.InterfaceSpec (duck-typed).  Host arrays are kept alive
+    in `keep` until mortar_setup has copied them."""
+    d = mortar_iface_desc()
+    k = _Keep()
+    k.fs = np.ascontiguousarray(spec.face_id_static, dtype=np.int32).ravel()
+    k.fm = np.ascontiguousarray(spec.face_id_moving, dtype=np.int32).ravel()
+    d.geometry = int(getattr(spec, "geometry", 0))
+    d.N, d.node_set = int(spec.N), int(spec.node_set)
+    d.n_par, d.n_perp = int(spec.n_par), int(spec.n_perp)
+    d.n_face_static, d.n_face_moving = int(spec.n_face_static), int(spec.n_face_moving)
+    d.face_id_static = k.fs.ctypes.data_as(_ip)
+    d.face_id_moving = k.fm.ctypes.data_as(_ip)
+    for name in ("owner_static", "owner_moving"):
+        arr = getattr(spec, name, None)
+        if arr is not None:
+            a = np.ascontiguousarray(arr, dtype=np.int32).ravel()
+            setattr(k, name, a)
+            setattr(d, name, a.ctypes.data_as(_ip))
+    d.l_par = float(spec.l_par)
+    for i in range(3):
+        d.normal[i] = float(spec.normal[i])
+    d.dS = float(spec.dS)
+    if getattr(spec, "metrics", None) is not None:
+        k.met = np.ascontiguousarray(spec.metrics, dtype=np.float64)
+        d.metrics = k.met.ctypes.data_as(_dp)
+    d.physics, d.riemann, d.precision = int(spec.physics), int(spec.riemann), int(spec.precision)
+    d.gamma, d.mu, d.Pr = float(spec.gamma), float(spec.mu), float(spec.Pr)
+    if keep is not None:
+        keep.append(k)
+    d._keep = k
+    return d
+
+
+# ---- convenience object (torch tensors in, torch tensors out) ------------------------
+
+class MortarOperator:
+    """Owns a library handle for a list of interfaces."""
+
+    def __init__(self, specs):
+        self.specs = list(specs)
+        keep = []
+        self.descs = [make_desc(s, keep) for s in self.specs]
+        self.h = mortar_setup(self.descs)
+        del keep
+
+    def close(self):
+        if self.h:
+            _check(mortar_destroy(self.h), "mortar_destroy")
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _stream(stream):
+        if stream is None:
+            import torch
+            return torch.cuda.current_stream().cuda_stream
+        return int(stream)
+
+    def update(self, disp, stream=None):
+        _check(mortar_update_displacement(self.h, disp, self._stream(stream)),
+               "mortar_update_displacement")
+
+    def update_ns(self, n, s, stream=None):
+        _check(mortar_update_displacement_ns(self.h, n, s, self._stream(stream)),
+               "mortar_update_displacement_ns")
+
+    def flux(self, Us, Um, Gs, Gm, Fs, Fm, stream=None):
+        p = lambda ts: None if ts is None else [None if t is None else t.data_ptr() for t in ts]  # noqa: E731
+        _check(mortar_flux(self.h, p(Us), p(Um), p(Gs), p(Gm), p(Fs), p(Fm), self._stream(stream)),
+               "mortar_flux")
+
+    def displacement(self, iface=0):
+        n = C.c_int64()
+        s = C.c_double()
+        _check(lib.mortar_get_displacement(self.h, iface, C.byref(n), C.byref(s)),
+               "mortar_get_displacement")
+        return int(n.value), float(s.value)
+
+    def index_map(self, iface=0, side=0):
+        sp = self.specs[iface]
+        F = sp.n_par * sp.n_perp
+        nf = sp.n_face_static if side == 0 else sp.n_face_moving
+        A = np.zeros((5, 2 * F), dtype=np.int32)
+        m = np.zeros((2, nf), dtype=np.int32)
+        _check(lib.mortar_get_index_map(self.h, iface, side, A.ctypes.data_as(_ip),
+                                        m.ctypes.data_as(_ip)), "mortar_get_index_map")
+        return A, m
+
+    def projection(self, iface=0):
+        NP = self.specs[iface].N + 1
+        Pf = np.zeros((4, NP, NP))
+        Pb = np.zeros((4, NP, NP))
+        _check(lib.mortar_get_projection(self.h, iface, Pf.ctypes.data_as(_dp),
+                                         Pb.ctypes.data_as(_dp)), "mortar_get_projection")
+        return Pf, Pb
+
+    def conservation(self, Fs, Fm, stream=None):
+        out = np.zeros((len(self.specs), 5, 3))
+        p = lambda ts: _ptrs([t.data_ptr() for t in ts])  # noqa: E731
+        _check(lib.mortar_conservation(self.h, p(Fs), p(Fm), out.ctypes.data_as(_dp),
+                                       C.c_void_p(self._stream(stream))), "mortar_conservation")
+        return out

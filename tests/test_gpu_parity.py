@@ -1,0 +1,194 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same seeded
+inputs, element by element, at sizes that span several tiles and a ragged tail; index
+maps bit-exact; the full-size benchmark workload on sampled rows."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2008_04356_amd import workloads as W
+
+from . import _parity as H
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2008_04356_amd import mortar
+    return mortar
+
+
+def _run_and_compare(M, spec, disps, seed=1, noise=1e-3, rows=None, check_maps=True):
+    op = M.MortarOperator([spec])
+    inp = W.make_inputs(spec, seed=seed, delta=disps[0], noise=noise)
+    din, oin = H.device_inputs(spec, inp), H.oracle_inputs(spec, inp)
+    worst = 0.0
+    try:
+        for d in disps:
+            print(f"[parity] {spec.name or 'spec'} N={spec.N} {spec.n_par}x{spec.n_perp} "
+                  f"prec={spec.precision} disp={d:.6g}", flush=True)
+            op.update([d])
+            n, s = O.decompose(d, spec.l_par)
+            assert op.displacement(0) == (n, s)
+            outs = H.gpu_flux(op, [spec], [din])
+            Fs, Fm = (outs[0][0].cpu().numpy(), outs[0][1].cpu().numpy())
+            ref = H.oracle_flux(spec, oin, n, s, rows=rows)
+            err = H.rel_err(spec, (Fs, Fm), ref, rows=rows)
+            worst = max(worst, float(np.max(err)))
+            assert np.max(err) <= H.TOL[spec.precision], (d, err)
+            # columns that are not on the interface stay untouched
+            for F, fid, nf in ((Fs, spec.face_id_static, spec.n_face_static),
+                               (Fm, spec.face_id_moving, spec.n_face_moving)):
+                off = np.setdiff1d(np.arange(nf), fid.ravel())
+                if off.size:
+                    assert np.all(np.isnan(F[:, :, off]))
+            if check_maps:
+                for side in (0, 1):
+                    A, m = op.index_map(0, side)
+                    own = spec.owner_moving if side == 0 else spec.owner_static
+                    fid = spec.face_id_static if side == 0 else spec.face_id_moving
+                    nf = spec.n_face_static if side == 0 else spec.n_face_moving
+                    Ao, mo = O.index_map(side, spec.n_par, spec.n_perp, n, fid, nf, own)
+                    assert np.array_equal(A, Ao) and np.array_equal(m, mo)
+    finally:
+        op.close()
+    return worst
+
+
+def test_c1_euler_lf_fp64_ten_stages(M):
+    specs, disp = W.config(1)
+    spec = specs[0]
+    W.seeded_owners(spec, seed=1, n_static_ranks=2, n_moving_ranks=3)
+    _run_and_compare(M, spec, [disp(k)[0] for k in range(10)], seed=1, noise=1e-4)
+
+
+@pytest.mark.parametrize("precision", [W.FP64, W.FP32])
+def test_ns_roe_multi_tile_ragged(M, precision):
+    # 70 faces along the slide: several tiles and a ragged last tile in both precisions
+    spec = W.make_plane(5, 70, 3, physics=W.NS, riemann=W.ROE, mu=1e-3, precision=precision,
+                        scramble_seed=2, extra_cols=5, name="ns-ragged")
+    W.seeded_owners(spec, seed=3, n_static_ranks=4, n_moving_ranks=5)
+    disps = [0.3137 * spec.l_par, 17.77 * spec.l_par, -3.25 * spec.l_par, 0.0, 69.0 * spec.l_par]
+    _run_and_compare(M, spec, disps, seed=7, noise=1e-3)
+
+
+@pytest.mark.parametrize("precision", [W.FP64, W.FP32])
+@pytest.mark.parametrize("N,node_set,physics,riemann", [
+    (1, W.GAUSS, W.EULER, W.ROE), (2, W.LGL, W.NS, W.ROE), (3, W.LGL, W.EULER, W.LF),
+    (4, W.GAUSS, W.NS, W.LF), (6, W.GAUSS, W.EULER, W.ROE), (7, W.LGL, W.NS, W.ROE),
+    (8, W.GAUSS, W.EULER, W.LF), (9, W.GAUSS, W.NS, W.ROE)])
+def test_degrees_node_sets_and_fluxes(M, precision, N, node_set, physics, riemann):
+    spec = W.make_plane(N, 23, 2, physics=physics, riemann=riemann, node_set=node_set,
+                        mu=1e-3 if physics == W.NS else 0.0, precision=precision,
+                        scramble_seed=N, extra_cols=1, name="degree")
+    _run_and_compare(M, spec, [0.41 * spec.l_par, 5.003 * spec.l_par], seed=N, noise=1e-3,
+                     check_maps=False)
+
+
+@pytest.mark.parametrize("precision", [W.FP64, W.FP32])
+def test_annulus_metrics(M, precision):
+    spec = W.make_annulus(7, 40, 3, seed=3, precision=precision, name="annulus")
+    _run_and_compare(M, spec, [0.37 * spec.l_par, 11.5 * spec.l_par], seed=3, noise=1e-3)
+
+
+@pytest.mark.parametrize("n_par", [1, 2, 3])
+def test_tiny_periodic_rows(M, n_par):
+    spec = W.make_plane(3, n_par, 2, physics=W.NS, riemann=W.ROE, mu=1e-3, precision=W.FP64,
+                        name="tiny")
+    _run_and_compare(M, spec, [0.0, 0.5 * spec.l_par, 7.25 * spec.l_par, -0.1 * spec.l_par],
+                     seed=5, noise=1e-3)
+
+
+def test_huge_displacement_via_ns_entry(M):
+    import torch
+    spec = W.make_plane(3, 16, 2, physics=W.EULER, riemann=W.ROE, precision=W.FP64, name="huge")
+    op = M.MortarOperator([spec])
+    try:
+        inp = W.make_inputs(spec, seed=2, noise=1e-3)
+        din, oin = H.device_inputs(spec, inp), H.oracle_inputs(spec, inp)
+        n, s = (1 << 53) + 5, 0.625
+        op.update_ns([n], [s])
+        outs = H.gpu_flux(op, [spec], [din])
+        ref = H.oracle_flux(spec, oin, n, s)
+        err = H.rel_err(spec, (outs[0][0].cpu().numpy(), outs[0][1].cpu().numpy()), ref)
+        assert np.max(err) <= 1e-12
+        with pytest.raises(M.MortarError):
+            op.update_ns([0], [1.0])
+        torch.cuda.synchronize()
+    finally:
+        op.close()
+
+
+def test_errors_and_determinism(M):
+    import torch
+    spec = W.make_plane(5, 40, 2, physics=W.NS, riemann=W.ROE, mu=1e-3, precision=W.FP32)
+    op = M.MortarOperator([spec])
+    try:
+        inp = W.make_inputs(spec, seed=9, noise=1e-3)
+        din = H.device_inputs(spec, inp)
+        with pytest.raises(M.MortarError, match="no displacement"):
+            H.gpu_flux(op, [spec], [din])
+        with pytest.raises(M.MortarError, match="invalid"):
+            op.update([float("nan")])
+        with pytest.raises(M.MortarError, match="invalid"):
+            op.update([float("inf")])
+        op.update([0.77 * spec.l_par])
+        a = H.gpu_flux(op, [spec], [din])
+        b = H.gpu_flux(op, [spec], [din])
+        for x, y in zip(a[0], b[0]):
+            assert torch.equal(x, y)
+        with pytest.raises(M.MortarError, match="invalid"):
+            op.flux([din["Us"]], [din["Um"]], None, None, [a[0][0]], [a[0][1]])
+    finally:
+        op.close()
+
+
+def test_projection_matrices_against_oracle(M):
+    for N, ns in ((3, W.GAUSS), (5, W.GAUSS), (4, W.LGL), (9, W.LGL)):
+        spec = W.make_plane(N, 8, 1, node_set=ns, precision=W.FP64)
+        op = M.MortarOperator([spec])
+        try:
+            for s in (0.0, 1e-7, 0.3, 0.999):
+                op.update_ns([2], [s])
+                Pf, Pb = op.projection(0)
+                ref = O.projection_matrices(N, ns, s)
+                assert np.max(np.abs(Pf - ref["Pf"])) < 1e-13
+                assert np.max(np.abs(Pb - ref["Pb"])) < 1e-13
+        finally:
+            op.close()
+
+
+@pytest.mark.parametrize("precision", [W.FP64, W.FP32])
+def test_conservation_on_device(M, precision):
+    spec = W.make_plane(5, 70, 3, physics=W.NS, riemann=W.ROE, mu=1e-3, precision=precision,
+                        scramble_seed=4, extra_cols=2)
+    op = M.MortarOperator([spec])
+    try:
+        inp = W.make_inputs(spec, seed=4, noise=1e-2)
+        din, oin = H.device_inputs(spec, inp), H.oracle_inputs(spec, inp)
+        op.update([2.345 * spec.l_par])
+        outs = H.gpu_flux(op, [spec], [din])
+        c = op.conservation([outs[0][0]], [outs[0][1]])[0]
+        if precision == W.FP64:
+            assert np.all(np.abs(c[:, 0] - c[:, 1]) <= 1e-13 * c[:, 2])
+        else:
+            assert np.all(np.abs(c[:, 0] - c[:, 1]) <= 1e-6 * c[:, 2])
+        # the device sums agree with the oracle's sums of the same arrays
+        co = O.conservation(spec, outs[0][0].double().cpu().numpy(), outs[0][1].double().cpu().numpy())
+        assert np.max(np.abs(c - co)) <= 1e-14 * np.max(np.abs(co))
+    finally:
+        op.close()
+
+
+@pytest.mark.parametrize("precision", [W.FP32, W.FP64])
+def test_benchmark_workload_full_size_sampled_rows(M, precision):
+    """The benchmark's plane N=5, 128x64, NS Roe+BR1 interface at full size, with the
+    benchmark's launch configuration; the oracle checks sampled rows (all rows are
+    computed by the same kernel)."""
+    specs, disp = W.config(2, precision=precision)
+    spec = specs[0]
+    for k in (1, 137):
+        _run_and_compare(M, spec, [disp(k)[0]], seed=2, noise=1e-4, rows=(5, 8),
+                         check_maps=(k == 137))
