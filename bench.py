@@ -34,7 +34,22 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-stages", type=int, default=10)
     p.add_argument("--rotate-bytes", type=float, default=1.2e9)
+    p.add_argument("--copy-calibration", type=float, default=0.0,
+                   help="only run a plain device copy of this many MB (counter calibration)")
     return p.parse_args()
+
+
+def copy_calibration(mb):
+    """A plain copy of known size: its FETCH_SIZE/WRITE_SIZE counters scale the counter
+    readings of the mortar kernel to bytes."""
+    import torch
+    n = int(mb * 1e6) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 5}))
 
 
 def algorithmic_bytes(spec):
@@ -152,6 +167,11 @@ def main():
                           "n_gpus": a.gpus}))
         sys.exit(2)
     import torch
+
+    if a.copy_calibration > 0:
+        torch.cuda.set_device(0)
+        copy_calibration(a.copy_calibration)
+        return
 
     from paper_2008_04356_amd import mortar as M
     from paper_2008_04356_amd import workloads as W

@@ -22,9 +22,14 @@ struct GasConsts {
     T kfac;   // mu * gamma / ((gamma - 1) Pr): heat conduction coefficient over R
 };
 
+// FP32 uses the hardware reciprocal and square root (about 1 ulp, well inside the FP32
+// tolerance); FP64 keeps IEEE division and square root.
 template <typename T> __device__ __forceinline__ T dsqrt(T x);
-template <> __device__ __forceinline__ float dsqrt<float>(float x) { return __builtin_sqrtf(x); }
+template <> __device__ __forceinline__ float dsqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
 template <> __device__ __forceinline__ double dsqrt<double>(double x) { return __builtin_sqrt(x); }
+template <typename T> __device__ __forceinline__ T drcp(T x);
+template <> __device__ __forceinline__ float drcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ double drcp<double>(double x) { return 1.0 / x; }
 
 template <typename T> __device__ __forceinline__ T dabs(T x) { return x < T(0) ? -x : x; }
 template <typename T> __device__ __forceinline__ T dmax(T a, T b) { return a > b ? a : b; }
@@ -41,7 +46,7 @@ __device__ __forceinline__ void side_state(const T *U, T nx, T ny, T nz, const G
                                            Side<T> &o)
 {
     o.r = U[0];
-    o.ir = T(1) / o.r;
+    o.ir = drcp(o.r);
     o.u[0] = U[1] * o.ir;
     o.u[1] = U[2] * o.ir;
     o.u[2] = U[3] * o.ir;
@@ -64,7 +69,7 @@ __device__ __forceinline__ T entropy_fixed(T lam, T lamL, T lamR)
 {
     const T delta = dmax(T(0), dmax(lam - lamL, lamR - lam));
     const T a = dabs(lam);
-    return (a < delta) ? T(0.5) * (lam * lam / delta + delta) : a;
+    return (a < delta) ? T(0.5) * (lam * lam * drcp(delta) + delta) : a;
 }
 
 // Convective numerical flux, RIEM = 0: local Lax-Friedrichs, 1: Roe + Harten-Hyman.
@@ -83,7 +88,7 @@ __device__ __forceinline__ void convective_flux(const T *UL, const T *UR, T nx, 
     }
     // Roe averages with sqrt(rho) weights
     const T sl = dsqrt(L.r), sr = dsqrt(R.r);
-    const T iw = T(1) / (sl + sr);
+    const T iw = drcp(sl + sr);
     const T wl = sl * iw, wr = sr * iw;
     T u[3];
 #pragma unroll
@@ -92,7 +97,7 @@ __device__ __forceinline__ void convective_flux(const T *UL, const T *UR, T nx, 
     const T q2h = T(0.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
     const T c2 = g.gm1 * (H - q2h);
     const T c = dsqrt(c2);
-    const T ic2 = T(1) / c2;
+    const T ic2 = drcp(c2);
     const T rho = sl * sr;
     const T un = u[0] * nx + u[1] * ny + u[2] * nz;
     // jumps
@@ -132,7 +137,7 @@ template <typename T>
 __device__ __forceinline__ void viscous_flux(const T *U, const T *G, T nx, T ny, T nz,
                                              const GasConsts<T> &g, T *Fv)
 {
-    const T ir = T(1) / U[0];
+    const T ir = drcp(U[0]);
     const T v0 = U[1] * ir, v1 = U[2] * ir, v2 = U[3] * ir;
     const T half_v2 = T(0.5) * (v0 * v0 + v1 * v1 + v2 * v2);
     const T p_over_r = g.gm1 * (U[4] * ir - half_v2);

@@ -1,122 +1,43 @@
 // Per-stage topology kernels of the mortar operator:
-//  - FP64 assembly of the face->mortar and mortar->face projection matrices for the
-//    current sub-face fraction s (Sec. 3.2, Eqs. for M, S, P; Sec. 4.4: between face
-//    crossings only these operators change);
+//  - FP64 projection matrices of the current s for inspection (the flux kernel
+//    assembles its own copy in its prologue with the same routine);
 //  - the device-side mortar sort (Sec. 4.4, Appendix A): sorted index array A and its
 //    inverse map m, rebuilt when the displacement crosses a whole face;
 //  - FP64 compensated conservation sums of the face fluxes of both sides.
+#include "assemble.h"
 #include "mortar_internal.h"
 
 namespace mortar {
 
 // ------------------------------------------------------------------------------------
-// Projection matrices
+// Projection matrices for inspection: the same device routine the flux kernel runs in
+// its prologue, written to the handle's FP64 buffer.
 // ------------------------------------------------------------------------------------
 
-// Lagrange basis l_j(xi) of the nodes in c, barycentric second form; exact at nodes.
-__device__ static void lagrange_all(const BasisConsts &c, int NP, double xi, double *l)
+template <int NP>
+__global__ void k_assemble_inspect(const BasisConsts *__restrict__ basis, double s,
+                                   char *__restrict__ params)
 {
-    for (int m = 0; m < NP; ++m) {
-        if (xi == c.x[m]) {
-            for (int j = 0; j < NP; ++j) l[j] = (j == m) ? 1.0 : 0.0;
-            return;
-        }
-    }
-    double den = 0.0;
-    for (int j = 0; j < NP; ++j) {
-        l[j] = c.bw[j] / (xi - c.x[j]);
-        den += l[j];
-    }
-    const double inv = 1.0 / den;
-    for (int j = 0; j < NP; ++j) l[j] *= inv;
-}
-
-// Face coordinate of mortar coordinate z on sub-interval k (slope, offset form):
-//   static i_sub 0: s z + (s - 1)        static i_sub 1: (1 - s) z + s
-//   moving i_sub 0: s z + (1 - s)        moving i_sub 1: (1 - s) z - s
-// The slope is the length ratio J_k of the sub-interval (weight of Eq. mortar->face).
-__device__ static inline void sub_map(int k, double s, double &slope, double &offset)
-{
-    switch (k) {
-    case 0: slope = s; offset = s - 1.0; break;
-    case 1: slope = 1.0 - s; offset = s; break;
-    case 2: slope = s; offset = 1.0 - s; break;
-    default: slope = 1.0 - s; offset = -s; break;
-    }
-}
-
-__global__ void k_assemble(const BasisConsts *__restrict__ basis, char *__restrict__ params,
-                           int NP, int64_t n, int32_t nmod, double s)
-{
-    __shared__ BasisConsts c;
-    __shared__ double S[4][kMaxNP * kMaxNP];    // S_k[i][q] = int l_i(xi_k(z)) l_q(z) dz
-    const int tid = threadIdx.x;
-    {
-        const double *src = reinterpret_cast<const double *>(basis);
-        double *dst = reinterpret_cast<double *>(&c);
-        for (int i = tid; i < (int)(sizeof(BasisConsts) / sizeof(double)); i += blockDim.x)
-            dst[i] = src[i];
-    }
-    __syncthreads();
+    __shared__ double work[8 * NP * NP];
     double *Pf = reinterpret_cast<double *>(params + kHeaderBytes);
-    double *Pb = Pf + 4 * NP * NP;
-    float *Pf32 = reinterpret_cast<float *>(Pb + 4 * NP * NP);
-    float *Pb32 = Pf32 + 4 * NP * NP;
-    const int NN = NP * NP;
-
-    // forward: Pf_k[q][j] = l_j(xi_k(x_q))  (exact L2 projection for equal degree)
-    for (int e = tid; e < 4 * NP; e += blockDim.x) {
-        const int k = e / NP, q = e % NP;
-        double a, b, l[kMaxNP];
-        sub_map(k, s, a, b);
-        lagrange_all(c, NP, a * c.x[q] + b, l);
-        for (int j = 0; j < NP; ++j) {
-            Pf[k * NN + q * NP + j] = l[j];
-            Pf32[k * NN + q * NP + j] = (float)l[j];
-        }
-    }
-    // S_k[i][q] = sum_r tw_r l_i(xi_k(t_r)) l_q(t_r)
-    for (int e = tid; e < 4 * NP; e += blockDim.x) {
-        const int k = e / NP, i = e % NP;
-        double a, b;
-        sub_map(k, s, a, b);
-        double acc[kMaxNP];
-        for (int q = 0; q < NP; ++q) acc[q] = 0.0;
-        for (int r = 0; r < NP; ++r) {
-            double l[kMaxNP];
-            lagrange_all(c, NP, a * c.t[r] + b, l);
-            const double wi = c.tw[r] * l[i];
-            for (int q = 0; q < NP; ++q) acc[q] += wi * c.Lt[r * kMaxNP + q];
-        }
-        for (int q = 0; q < NP; ++q) S[k][i * kMaxNP + q] = acc[q];
-    }
-    __syncthreads();
-    // backward: Pb_k[j][q] = J_k sum_i Minv[j][i] S_k[i][q]
-    for (int e = tid; e < 4 * NN; e += blockDim.x) {
-        const int k = e / NN, j = (e % NN) / NP, q = e % NP;
-        double a, b;
-        sub_map(k, s, a, b);
-        double acc = 0.0;
-        for (int i = 0; i < NP; ++i) acc += c.Minv[j * kMaxNP + i] * S[k][i * kMaxNP + q];
-        Pb[k * NN + j * NP + q] = a * acc;
-        Pb32[k * NN + j * NP + q] = (float)(a * acc);
-    }
-    if (tid == 0) {
-        ParamHeader *h = reinterpret_cast<ParamHeader *>(params);
-        h->nmod = nmod;
-        h->NP = NP;
-        h->n = n;
-        h->s = s;
-        h->pad = 0.0;
-    }
+    assemble_matrices<NP, double>(basis, s, work, Pf, Pf + 4 * NP * NP, (double *)nullptr,
+                                  (double *)nullptr);
 }
 
 hipError_t launch_assemble(const Iface &f, hipStream_t st)
 {
-    const int64_t np = f.d.n_par;
-    const int32_t nmod = (int32_t)(((f.n % np) + np) % np);
-    hipLaunchKernelGGL(k_assemble, dim3(1), dim3(128), 0, st, f.d_basis, f.d_params, f.NP, f.n,
-                       nmod, f.s);
+#define MORTAR_ASM_CASE(np)                                                                   \
+    case np:                                                                                  \
+        hipLaunchKernelGGL(k_assemble_inspect<np>, dim3(1), dim3(128), 0, st, f.d_basis, f.s, \
+                           f.d_params);                                                       \
+        break;
+    switch (f.NP) {
+        MORTAR_ASM_CASE(2) MORTAR_ASM_CASE(3) MORTAR_ASM_CASE(4) MORTAR_ASM_CASE(5)
+        MORTAR_ASM_CASE(6) MORTAR_ASM_CASE(7) MORTAR_ASM_CASE(8) MORTAR_ASM_CASE(9)
+        MORTAR_ASM_CASE(10)
+    default: return hipErrorInvalidValue;
+    }
+#undef MORTAR_ASM_CASE
     return hipGetLastError();
 }
 

@@ -14,8 +14,10 @@ hipError_t launch_flux_f32(const FluxArgs<float> &a, int NP, int grid, bool ns, 
                            int riem, hipStream_t st);
 hipError_t launch_flux_f64(const FluxArgs<double> &a, int NP, int grid, bool ns, bool met,
                            int riem, hipStream_t st);
-int flux_tile_faces_f32(int NP, bool ns, bool met);
-int flux_tile_faces_f64(int NP, bool ns, bool met);
+int flux_tile_capacity_f32(int NP, bool ns, bool met);
+int flux_tile_capacity_f64(int NP, bool ns, bool met);
+int flux_occupancy_f32(int NP, bool ns, bool met, int riem);
+int flux_occupancy_f64(int NP, bool ns, bool met, int riem);
 
 // ------------------------------------------------------------------------------------
 // FP64 node sets by bracketing and bisection (roots of P_NP for Gauss, of P_N' for
@@ -306,6 +308,12 @@ static int setup_one(const mortar_iface_desc &d, Iface &f)
     const int R = std::max(f.R_s, f.R_m);
     if (hipMalloc((void **)&f.d_hist, sizeof(int32_t) * (size_t)R * f.n_sort_blocks) != hipSuccess)
         return MORTAR_ERR_OOM;
+    {
+        const bool ns = d.physics == MORTAR_NAVIER_STOKES, met = d.metrics != nullptr;
+        const int riem = d.riemann == MORTAR_FLUX_ROE;
+        f.flux_occ = f.elem == 8 ? flux_occupancy_f64(f.NP, ns, met, riem)
+                                 : flux_occupancy_f32(f.NP, ns, met, riem);
+    }
     f.n_cons_blocks = std::min(256, std::max(1, (f.F + 255) / 256));
     if (hipMalloc((void **)&f.d_cons, sizeof(double) * 30 * (size_t)f.n_cons_blocks) != hipSuccess)
         return MORTAR_ERR_OOM;
@@ -341,7 +349,6 @@ static int apply_update(Handle *h, const int64_t *n, const double *s, hipStream_
             TRY_HIP(launch_index_map(f, 1, st));
             f.nmod_built = nmod;
         }
-        TRY_HIP(launch_assemble(f, st));
         f.ready = true;
     }
     return MORTAR_OK;
@@ -409,7 +416,9 @@ int mortar_setup(const mortar_iface_desc *desc, int n_iface, mortar_handle **out
     if (rc) return rc;
     mortar_handle *h = new (std::nothrow) mortar_handle();
     if (!h) return MORTAR_ERR_OOM;
-    if (hipGetDevice(&h->device) != hipSuccess) {
+    if (hipGetDevice(&h->device) != hipSuccess ||
+        hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, h->device) !=
+            hipSuccess) {
         delete h;
         return MORTAR_ERR_HIP;
     }
@@ -469,8 +478,8 @@ int mortar_flux(mortar_handle *h, const void *const *U_s, const void *const *U_m
         const bool ns = f.d.physics == MORTAR_NAVIER_STOKES;
         if (!U_s[i] || !U_m[i] || !F_s[i] || !F_m[i]) return MORTAR_ERR_INVALID_ARG;
         if (ns && (!G_s || !G_m || !G_s[i] || !G_m[i])) return MORTAR_ERR_INVALID_ARG;
-        TRY_HIP(launch_flux(f, U_s[i], U_m[i], ns ? G_s[i] : nullptr, ns ? G_m[i] : nullptr,
-                            F_s[i], F_m[i], st));
+        TRY_HIP(launch_flux(f, h->n_cu, U_s[i], U_m[i], ns ? G_s[i] : nullptr,
+                            ns ? G_m[i] : nullptr, F_s[i], F_m[i], st));
     }
     return MORTAR_OK;
 }
@@ -502,6 +511,7 @@ int mortar_get_projection(mortar_handle *h, int iface, double *Pf, double *Pb)
     if (!h || iface < 0 || iface >= (int)h->ifs.size()) return MORTAR_ERR_INVALID_ARG;
     const Iface &f = h->ifs[iface];
     if (!f.ready) return MORTAR_ERR_NOT_READY;
+    TRY_HIP(launch_assemble(f, nullptr));
     TRY_HIP(hipDeviceSynchronize());
     const size_t nn = (size_t)4 * f.NP * f.NP;
     if (Pf) TRY_HIP(hipMemcpy(Pf, f.d_params + off_f64(f.NP), sizeof(double) * nn, hipMemcpyDeviceToHost));
@@ -539,7 +549,7 @@ int mortar_conservation(mortar_handle *h, const void *const *F_s, const void *co
 
 namespace mortar {
 
-hipError_t launch_flux(const Iface &f, const void *Us, const void *Um, const void *Gs,
+hipError_t launch_flux(const Iface &f, int n_cu, const void *Us, const void *Um, const void *Gs,
                        const void *Gm, void *Fs, void *Fm, hipStream_t st)
 {
     const bool ns = f.d.physics == MORTAR_NAVIER_STOKES;
@@ -547,36 +557,43 @@ hipError_t launch_flux(const Iface &f, const void *Us, const void *Um, const voi
     const int riem = f.d.riemann == MORTAR_FLUX_ROE ? 1 : 0;
     const double gm1 = f.d.gamma - 1.0;
     const double kfac = ns ? f.d.mu * f.d.gamma / (gm1 * f.d.Pr) : 0.0;
-    if (f.elem == 8) {
-        FluxArgs<double> a;
-        a.Us = (const double *)Us; a.Um = (const double *)Um;
-        a.Gs = (const double *)Gs; a.Gm = (const double *)Gm;
-        a.met = (const double *)f.d_metrics;
-        a.Fs = (double *)Fs; a.Fm = (double *)Fm;
-        a.fid_s = f.d_fid_s; a.fid_m = f.d_fid_m; a.params = f.d_params;
+    const int64_t np = f.d.n_par;
+    const int nmod = (int)(((f.n % np) + np) % np);
+    const int cap = f.elem == 8 ? flux_tile_capacity_f64(f.NP, ns, met)
+                                : flux_tile_capacity_f32(f.NP, ns, met);
+    if (cap <= 0) return hipErrorInvalidValue;
+    // balanced tiles: as few as the capacity allows, all of nearly equal length
+    const int tiles_per_row = (f.d.n_par + cap - 1) / cap;
+    const int tile_len = (f.d.n_par + tiles_per_row - 1) / tiles_per_row;
+    const int n_tiles = tiles_per_row * f.NP * f.d.n_perp;
+    const int grid = std::max(1, std::min(n_tiles, f.flux_occ * n_cu));
+    auto fill = [&](auto &a, auto zero) {
+        using T = decltype(zero);
+        a.Us = (const T *)Us; a.Um = (const T *)Um;
+        a.Gs = (const T *)Gs; a.Gm = (const T *)Gm;
+        a.met = (const T *)f.d_metrics;
+        a.Fs = (T *)Fs; a.Fm = (T *)Fm;
+        a.fid_s = f.d_fid_s; a.fid_m = f.d_fid_m;
+        a.basis = f.d_basis;
+        a.s = f.s;
+        a.nmod = nmod;
         a.n_par = f.d.n_par; a.n_perp = f.d.n_perp;
         a.nfs = f.d.n_face_static; a.nfm = f.d.n_face_moving;
-        const int tf = flux_tile_faces_f64(f.NP, ns, met);
-        a.tiles_per_row = (f.d.n_par + tf - 1) / tf;
-        a.nx = f.d.normal[0]; a.ny = f.d.normal[1]; a.nz = f.d.normal[2]; a.dS = f.d.dS;
-        a.gas = {gm1, f.d.gamma, ns ? f.d.mu : 0.0, kfac};
-        const int grid = a.tiles_per_row * f.NP * f.d.n_perp;
+        a.tiles_per_row = tiles_per_row;
+        a.tile_len = tile_len;
+        a.n_tiles = n_tiles;
+        a.tiles_per_xcd = (n_tiles + kXcds - 1) / kXcds;
+        a.nx = (T)f.d.normal[0]; a.ny = (T)f.d.normal[1]; a.nz = (T)f.d.normal[2];
+        a.dS = (T)f.d.dS;
+        a.gas = {(T)gm1, (T)f.d.gamma, (T)(ns ? f.d.mu : 0.0), (T)kfac};
+    };
+    if (f.elem == 8) {
+        FluxArgs<double> a;
+        fill(a, 0.0);
         return launch_flux_f64(a, f.NP, grid, ns, met, riem, st);
     }
     FluxArgs<float> a;
-    a.Us = (const float *)Us; a.Um = (const float *)Um;
-    a.Gs = (const float *)Gs; a.Gm = (const float *)Gm;
-    a.met = (const float *)f.d_metrics;
-    a.Fs = (float *)Fs; a.Fm = (float *)Fm;
-    a.fid_s = f.d_fid_s; a.fid_m = f.d_fid_m; a.params = f.d_params;
-    a.n_par = f.d.n_par; a.n_perp = f.d.n_perp;
-    a.nfs = f.d.n_face_static; a.nfm = f.d.n_face_moving;
-    const int tf = flux_tile_faces_f32(f.NP, ns, met);
-    a.tiles_per_row = (f.d.n_par + tf - 1) / tf;
-    a.nx = (float)f.d.normal[0]; a.ny = (float)f.d.normal[1]; a.nz = (float)f.d.normal[2];
-    a.dS = (float)f.d.dS;
-    a.gas = {(float)gm1, (float)f.d.gamma, (float)(ns ? f.d.mu : 0.0), (float)kfac};
-    const int grid = a.tiles_per_row * f.NP * f.d.n_perp;
+    fill(a, 0.0f);
     return launch_flux_f32(a, f.NP, grid, ns, met, riem, st);
 }
 

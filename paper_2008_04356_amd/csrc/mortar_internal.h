@@ -69,17 +69,19 @@ struct Iface {
     bool ready = false;
     double *d_cons = nullptr;          // conservation partials
     int n_cons_blocks = 0;
+    int flux_occ = 1;                  // resident flux workgroups per CU
 };
 
 struct Handle {
     int device = 0;
+    int n_cu = 256;
     std::vector<Iface> ifs;
 };
 
 // ---- launchers (kernels in k_*.hip) ------------------------------------------------
 hipError_t launch_assemble(const Iface &f, hipStream_t st);
 hipError_t launch_index_map(Iface &f, int side, hipStream_t st);
-hipError_t launch_flux(const Iface &f, const void *Us, const void *Um, const void *Gs,
+hipError_t launch_flux(const Iface &f, int n_cu, const void *Us, const void *Um, const void *Gs,
                        const void *Gm, void *Fs, void *Fm, hipStream_t st);
 hipError_t launch_conservation(const Iface &f, const void *Fs, const void *Fm, double *d_out,
                                hipStream_t st);
