@@ -3,7 +3,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <cstdlib>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "k_flux.h"
@@ -18,6 +20,12 @@ int flux_tile_capacity_f32(int NP, bool ns, bool met);
 int flux_tile_capacity_f64(int NP, bool ns, bool met);
 int flux_occupancy_f32(int NP, bool ns, bool met, int riem);
 int flux_occupancy_f64(int NP, bool ns, bool met, int riem);
+int flux_mfma_occupancy_f32(int NP, bool ns, bool met, int riem);
+int flux_mfma_occupancy_f64(int NP, bool ns, bool met, int riem);
+hipError_t launch_flux_mfma_f32(const FluxArgs<float> &a, int NP, int grid, bool ns, bool met,
+                                int riem, hipStream_t st);
+hipError_t launch_flux_mfma_f64(const FluxArgs<double> &a, int NP, int grid, bool ns, bool met,
+                                int riem, hipStream_t st);
 
 // ------------------------------------------------------------------------------------
 // FP64 node sets by bracketing and bisection (roots of P_NP for Gauss, of P_N' for
@@ -311,8 +319,14 @@ static int setup_one(const mortar_iface_desc &d, Iface &f)
     {
         const bool ns = d.physics == MORTAR_NAVIER_STOKES, met = d.metrics != nullptr;
         const int riem = d.riemann == MORTAR_FLUX_ROE;
-        f.flux_occ = f.elem == 8 ? flux_occupancy_f64(f.NP, ns, met, riem)
-                                 : flux_occupancy_f32(f.NP, ns, met, riem);
+        const char *kv = std::getenv("MORTAR_FLUX_KERNEL");
+        f.flux_variant = (kv && std::string(kv) == "mfma") ? 1 : 0;
+        if (f.flux_variant == 0)
+            f.flux_occ = f.elem == 8 ? flux_occupancy_f64(f.NP, ns, met, riem)
+                                     : flux_occupancy_f32(f.NP, ns, met, riem);
+        else
+            f.flux_occ = f.elem == 8 ? flux_mfma_occupancy_f64(f.NP, ns, met, riem)
+                                     : flux_mfma_occupancy_f32(f.NP, ns, met, riem);
     }
     f.n_cons_blocks = std::min(256, std::max(1, (f.F + 255) / 256));
     if (hipMalloc((void **)&f.d_cons, sizeof(double) * 30 * (size_t)f.n_cons_blocks) != hipSuccess)
@@ -559,8 +573,9 @@ hipError_t launch_flux(const Iface &f, int n_cu, const void *Us, const void *Um,
     const double kfac = ns ? f.d.mu * f.d.gamma / (gm1 * f.d.Pr) : 0.0;
     const int64_t np = f.d.n_par;
     const int nmod = (int)(((f.n % np) + np) % np);
-    const int cap = f.elem == 8 ? flux_tile_capacity_f64(f.NP, ns, met)
-                                : flux_tile_capacity_f32(f.NP, ns, met);
+    const int cap = f.flux_variant == 1 ? 15
+                  : (f.elem == 8 ? flux_tile_capacity_f64(f.NP, ns, met)
+                                 : flux_tile_capacity_f32(f.NP, ns, met));
     if (cap <= 0) return hipErrorInvalidValue;
     // balanced tiles: as few as the capacity allows, all of nearly equal length
     const int tiles_per_row = (f.d.n_par + cap - 1) / cap;
@@ -590,11 +605,13 @@ hipError_t launch_flux(const Iface &f, int n_cu, const void *Us, const void *Um,
     if (f.elem == 8) {
         FluxArgs<double> a;
         fill(a, 0.0);
-        return launch_flux_f64(a, f.NP, grid, ns, met, riem, st);
+        return f.flux_variant == 1 ? launch_flux_mfma_f64(a, f.NP, grid, ns, met, riem, st)
+                                   : launch_flux_f64(a, f.NP, grid, ns, met, riem, st);
     }
     FluxArgs<float> a;
     fill(a, 0.0f);
-    return launch_flux_f32(a, f.NP, grid, ns, met, riem, st);
+    return f.flux_variant == 1 ? launch_flux_mfma_f32(a, f.NP, grid, ns, met, riem, st)
+                               : launch_flux_f32(a, f.NP, grid, ns, met, riem, st);
 }
 
 }  // namespace mortar

@@ -70,6 +70,7 @@ struct Iface {
     double *d_cons = nullptr;          // conservation partials
     int n_cons_blocks = 0;
     int flux_occ = 1;                  // resident flux workgroups per CU
+    int flux_variant = 1;              // 0: VALU projections, 1: matrix-core projections
 };
 
 struct Handle {
