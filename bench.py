@@ -34,6 +34,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-stages", type=int, default=10)
     p.add_argument("--rotate-bytes", type=float, default=1.2e9)
+    p.add_argument("--graph", action="store_true", help="replay a captured HIP graph per stage")
     p.add_argument("--copy-calibration", type=float, default=0.0,
                    help="only run a plain device copy of this many MB (counter calibration)")
     return p.parse_args()
@@ -64,35 +65,61 @@ def algorithmic_bytes(spec):
     return total
 
 
-def run_leg(M, W, specs, disp, steps, warmup, rotate_bytes):
+def run_leg(M, W, specs, disp, steps, warmup, rotate_bytes, graph=False, plain=False):
+    """Times one precision of a workload.  plain: one handle (one launch) per interface
+    instead of the batched persistent launch; graph: each stage replays a captured HIP
+    graph instead of eager launches."""
     import numpy as np
     import torch
 
-    spec = specs[0]
-    op = M.MortarOperator(specs)
-    dt = torch.float64 if spec.precision == W.FP64 else torch.float32
+    ops = [M.MortarOperator([s]) for s in specs] if plain else [M.MortarOperator(specs)]
     t0 = time.time()
-    inp = W.make_inputs(spec, seed=2, delta=disp(0)[0], noise=1e-4)
-    base = {k: None if v is None else torch.from_numpy(W.round_to(v, spec.precision)).cuda()
-            for k, v in inp.items()}
-    del inp
-    set_bytes = algorithmic_bytes(spec)
+    base = []
+    for i, spec in enumerate(specs):
+        inp = W.make_inputs(spec, seed=2 + i, delta=disp(0)[i], noise=1e-4)
+        base.append({k: None if v is None else torch.from_numpy(W.round_to(v, spec.precision)).cuda()
+                     for k, v in inp.items()})
+        del inp
+    set_bytes = sum(algorithmic_bytes(s) for s in specs)
     nsets = max(2, int(np.ceil(rotate_bytes / set_bytes)))
     sets = []
     for r in range(nsets):
-        d = {k: None if v is None else v.clone() for k, v in base.items()}
-        d["Fs"] = torch.zeros((5, spec.P, spec.n_face_static), dtype=dt, device="cuda")
-        d["Fm"] = torch.zeros((5, spec.P, spec.n_face_moving), dtype=dt, device="cuda")
-        sets.append(d)
+        per = []
+        for spec, b in zip(specs, base):
+            dt = torch.float64 if spec.precision == W.FP64 else torch.float32
+            d = {k: None if v is None else v.clone() for k, v in b.items()}
+            d["Fs"] = torch.zeros((5, spec.P, spec.n_face_static), dtype=dt, device="cuda")
+            d["Fm"] = torch.zeros((5, spec.P, spec.n_face_moving), dtype=dt, device="cuda")
+            per.append(d)
+        sets.append(per)
     del base
     torch.cuda.synchronize()
-    print(f"[bench] {spec.name} prec={spec.precision} sets={nsets} x {set_bytes / 1e6:.1f} MB "
-          f"(setup {time.time() - t0:.1f} s)", file=sys.stderr, flush=True)
+    print(f"[bench] {'+'.join(s.name for s in specs)} prec={specs[0].precision} sets={nsets} x "
+          f"{set_bytes / 1e6:.1f} MB graph={graph} plain={plain} (setup {time.time() - t0:.1f} s)",
+          file=sys.stderr, flush=True)
+
+    def args(per, sel=None):
+        sel = range(len(specs)) if sel is None else sel
+        return ([per[i]["Us"] for i in sel], [per[i]["Um"] for i in sel], [per[i]["Gs"] for i in sel],
+                [per[i]["Gm"] for i in sel], [per[i]["Fs"] for i in sel], [per[i]["Fm"] for i in sel])
+
+    graphs = None
+    if graph:
+        ops[0].update(disp(0))
+        graphs = [ops[0].graph(*args(per)) for per in sets]
 
     def step(k):
-        d = sets[k % nsets]
-        op.update(disp(k))
-        op.flux([d["Us"]], [d["Um"]], [d["Gs"]], [d["Gm"]], [d["Fs"]], [d["Fm"]])
+        per = sets[k % nsets]
+        d = disp(k)
+        if graph:
+            graphs[k % nsets].launch(d)
+        elif plain:
+            for i, op in enumerate(ops):
+                op.update([d[i]])
+                op.flux(*args(per, [i]))
+        else:
+            ops[0].update(d)
+            ops[0].flux(*args(per))
 
     for k in range(warmup):
         step(k)
@@ -105,23 +132,38 @@ def run_leg(M, W, specs, disp, steps, warmup, rotate_bytes):
     torch.cuda.synchronize()
     ms_step = e0.elapsed_time(e1) / steps
 
-    # dominant kernel: the fused flux launch, timed with HIP events on the stream it runs on
+    # the fused flux launch(es) alone, timed with HIP events on the stream they run on
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(steps)]
-    op.update(disp(warmup + steps))
+    d = disp(warmup + steps)
+    for i, op in enumerate(ops):
+        op.update([d[i]] if plain else d)
     for k in range(steps):
-        d = sets[k % nsets]
+        per = sets[k % nsets]
         evs[k][0].record()
-        op.flux([d["Us"]], [d["Um"]], [d["Gs"]], [d["Gm"]], [d["Fs"]], [d["Fm"]])
+        if plain:
+            for i, op in enumerate(ops):
+                op.flux(*args(per, [i]))
+        else:
+            ops[0].flux(*args(per))
         evs[k][1].record()
     torch.cuda.synchronize()
     kms = np.array([a.elapsed_time(b) for a, b in evs])
-    conservation = op.conservation([sets[0]["Fs"]], [sets[0]["Fm"]])[0]
-    op.close()
-    pts = spec.mortar_points
+    cons = []
+    for i, op in enumerate(ops):
+        sel = [i] if plain else range(len(specs))
+        c = op.conservation([sets[0][j]["Fs"] for j in sel], [sets[0][j]["Fm"] for j in sel])
+        cons.append(c)
+    cons = np.concatenate(cons, axis=0)
+    cons_rel = float(np.max(np.abs(cons[:, :, 0] - cons[:, :, 1]) / cons[:, :, 2]))
+    if graphs:
+        for g in graphs:
+            g.close()
+    for op in ops:
+        op.close()
+    pts = sum(s.mortar_points for s in specs)
     kavg = float(np.mean(kms))
     achieved = set_bytes / (kavg * 1e-3) / 1e9
-    cons_rel = float(np.max(np.abs(conservation[:, 0] - conservation[:, 1]) / conservation[:, 2]))
     return {
         "pts_per_s": pts / (ms_step * 1e-3),
         "ms_per_step": ms_step,
@@ -178,15 +220,28 @@ def main():
 
     torch.cuda.set_device(0)
     specs32, disp = W.config(a.config, precision=W.FP32)
-    r32 = run_leg(M, W, specs32, disp, a.steps, a.warmup, a.rotate_bytes)
+    r32 = run_leg(M, W, specs32, disp, a.steps, a.warmup, a.rotate_bytes, graph=a.graph)
     r64 = None
     if not a.no_fp64:
         specs64, _ = W.config(a.config, precision=W.FP64)
-        r64 = run_leg(M, W, specs64, disp, a.steps, a.warmup, a.rotate_bytes)
+        # the comparison point: plain FP64, one launch per interface
+        r64 = run_leg(M, W, specs64, disp, a.steps, a.warmup, a.rotate_bytes, plain=True)
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(W, specs64 if r64 else specs32, disp, a.cpu_stages)
+    kname = {1: "k_mortar_flux<float,4,Euler,LF>", 2: "k_mortar_flux<float,6,NS,Roe>",
+             3: "k_mortar_flux<float,8,NS+metrics,Roe>", 4: "k_mortar_flux_batch<float,NS,Roe,N=3,5,7>",
+             5: "k_mortar_flux<float,10,Euler,Roe>"}
     spec = specs32[0]
+    names = {2: f"plane sliding interface N={spec.N}, {spec.n_par}x{spec.n_perp} face pairs, "
+                "Navier-Stokes Roe+BR1 (mu=1e-4), displacement 0.0137 l_par per stage, FP32",
+             3: f"plane annular axial interface N={spec.N}, {spec.n_par}x{spec.n_perp} face pairs, "
+                "per-point metrics, Navier-Stokes Roe+BR1, FP32",
+             4: "turbine-like batch: annulus N=7 320x125 + annulus N=5 256x72 + plane N=3 64x32, "
+                "Navier-Stokes Roe+BR1, FP32, one persistent launch per stage"
+                + (" (HIP graph)" if a.graph else ""),
+             1: f"plane interface N={spec.N}, {spec.n_par}x{spec.n_perp}, Euler LF, FP32",
+             5: f"plane interface N={spec.N}, {spec.n_par}x{spec.n_perp}, Euler Roe, FP32"}
     out = {
         "metric": "mortar flux points/sec and HBM GB/s vs peak, batched FP32 vs plain FP64",
         "value": r32["pts_per_s"],
@@ -200,10 +255,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"plane sliding interface N={spec.N}, {spec.n_par}x{spec.n_perp} "
-                               "face pairs, Navier-Stokes Roe+BR1 (mu=1e-4), displacement "
-                               "0.0137 l_par per stage, FP32",
-                   "mortar_points_per_step": spec.mortar_points,
+        "config": {"workload": names.get(a.config, f"config {a.config}"),
+                   "mortar_points_per_step": sum(s.mortar_points for s in specs32),
                    "fp64": None if r64 is None else {
                        "value": r64["pts_per_s"], "ms_per_step": r64["ms_per_step"],
                        "kernel_ms_avg": r64["kernel_ms_avg"], "achieved_GBs": r64["achieved_GBs"],
@@ -216,7 +269,7 @@ def main():
                                                        "rotated_sets")}},
         "roofline": {"bound": "hbm", "achieved": r32["achieved_GBs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": r32["frac"], "traffic": None,
-                     "kernel": "k_mortar_flux<float,6,NS,Roe>",
+                     "kernel": kname.get(a.config),
                      "bytes_per_launch": r32["bytes_per_launch"]},
         "cpu_baseline": cpu,
     }

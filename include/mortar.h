@@ -121,6 +121,23 @@ int mortar_flux(mortar_handle *h, const void *const *U_s, const void *const *U_m
                 const void *const *G_s, const void *const *G_m, void *const *F_s,
                 void *const *F_m, void *stream);
 
+/* ---- one stage as a HIP graph (batched persistent launch, Sec. 4.4 multi-interface) --
+ * mortar_graph_create captures the flux launch of every interface (one persistent
+ * launch when the interfaces share element type, physics and flux) for the given fixed
+ * device buffers (same conventions as mortar_flux) into an executable graph; it needs a
+ * displacement already set.  mortar_graph_launch then runs one stage: the displacement
+ * update of mortar_update_displacement (host split; index maps rebuilt on face crossings,
+ * launched on stream before the graph) followed by the graph with the new fraction s
+ * written into its kernel arguments.  The graph owns no face buffers; destroy it before
+ * its handle.  Errors as for mortar_flux; a graph whose launch shape no longer fits
+ * reports UNSUPPORTED. */
+typedef struct mortar_graph mortar_graph;
+int mortar_graph_create(mortar_handle *h, const void *const *U_s, const void *const *U_m,
+                        const void *const *G_s, const void *const *G_m, void *const *F_s,
+                        void *const *F_m, mortar_graph **out);
+int mortar_graph_launch(mortar_graph *g, const double *disp, void *stream);
+int mortar_graph_destroy(mortar_graph *g);
+
 /* Frees the handle and its device buffers (synchronizes the device first). */
 int mortar_destroy(mortar_handle *h);
 

@@ -45,7 +45,6 @@ struct FluxArgs {
     int n_par, n_perp, nfs, nfm;
     int tiles_per_row, tile_len;  // tile_len <= the compile-time tile capacity
     int n_tiles;                  // tiles_per_row * NP * n_perp
-    int tiles_per_xcd;            // ceil(n_tiles / kXcds): contiguous tile range per XCD
     T nx, ny, nz, dS;
     GasConsts<T> gas;
 };
@@ -54,21 +53,32 @@ constexpr int kFluxThreads = 256;
 constexpr int kHalf = kFluxThreads / 2;
 constexpr int kXcds = 8;   // MI355X: workgroups are dispatched round-robin over 8 XCDs
 
-// Persistent schedule.  Workgroup b runs on XCD b % 8 and takes the tiles of that XCD's
-// contiguous range in steps of the number of workgroups on the XCD, so at any time the
-// workgroups of one XCD work on neighbouring tiles of the same line: the cache lines a
-// tile shares with its neighbours (its halo faces, and the partial lines at its ends)
-// are then fetched into that XCD's L2 once.
+// LDS budget per workgroup of the VALU-projection kernel: 48 KB in FP32 (three
+// workgroups per CU), 80 KB in FP64 (two).
+template <typename T> constexpr int lds_budget() { return sizeof(T) == 8 ? 81920 : 49152; }
+
+// Degree sets of the batched kernel: every degree, or the 1.5-stage turbine set N = 3, 5, 7.
+constexpr int kMaskAll = 0x7FC;
+constexpr int kMaskTurbine = (1 << 4) | (1 << 6) | (1 << 8);
+
+// Persistent schedule over the n tiles of one interface.  Workgroup b runs on XCD b % 8
+// (workgroups are dispatched round-robin over the XCDs); XCD x owns the contiguous eighth
+// [x*ceil(n/8), (x+1)*ceil(n/8)) of the tiles and its workgroups take them in steps of
+// the number of workgroups on that XCD.  So at any time the workgroups of one XCD work
+// on neighbouring tiles of the same line (the cache lines a tile shares with its
+// neighbours - halo faces, partial lines at its ends - are fetched into that XCD's L2
+// once), and with several interfaces every XCD gets the same share of each.
 struct TileCursor {
-    int xcd, base, stride, k, limit;
-    __device__ TileCursor(int n_tiles, int per_xcd)
+    int k, limit, stride;
+    __device__ explicit TileCursor(int n)
     {
         const int g = gridDim.x;
-        xcd = blockIdx.x % kXcds;
+        const int xcd = blockIdx.x % kXcds;
         const int local = blockIdx.x / kXcds;
         stride = g / kXcds + ((g % kXcds) > xcd ? 1 : 0);   // workgroups on this XCD
-        base = xcd * per_xcd;
-        limit = min(n_tiles, base + per_xcd);
+        const int per = (n + kXcds - 1) / kXcds;
+        const int base = xcd * per;
+        limit = min(n, base + per);
         k = base + local;
     }
     __device__ bool valid() const { return k < limit; }
@@ -172,21 +182,29 @@ __device__ __forceinline__ void prefetch(const FluxArgs<T> &a, const TileGeom &g
     }
 }
 
+// LDS bytes of one instantiation (state region + matrices).
+template <typename T, int NP, bool NSV, bool MET, int BUDGET>
+constexpr size_t flux_smem_bytes()
+{
+    using C = FluxCfg<T, NP, NSV, MET, BUDGET>;
+    return ((size_t)C::LDS_T * sizeof(T) + 15) / 16 * 16 + (size_t)8 * C::NN * sizeof(T);
+}
+
+// All tiles of one interface that this workgroup's cursor visits (the cursor is valid
+// on entry).  smem holds flux_smem_bytes() bytes, 16-aligned.  Ends with a barrier, so
+// the caller may reuse smem at once.
 template <typename T, int NP, bool NSV, bool MET, int RIEM, int BUDGET>
-__global__ __launch_bounds__(kFluxThreads) void k_mortar_flux(FluxArgs<T> a)
+__device__ __forceinline__ void run_interface(const FluxArgs<T> &a, TileCursor &cur, char *smem)
 {
     using C = FluxCfg<T, NP, NSV, MET, BUDGET>;
     constexpr int V = C::V, VS = C::VS, NN = C::NN, TF = C::TF, LD = C::LD, P = NN;
     static_assert(C::LDS_T * sizeof(T) >= 8 * NN * sizeof(double), "assembly scratch");
 
-    __shared__ __attribute__((aligned(16))) T lds[C::LDS_T];
-    __shared__ T mats[8 * NN];              // Pf[4][NP][NP], Pb[4][NP][NP] in T
+    T *lds = reinterpret_cast<T *>(smem);
+    T *mats = reinterpret_cast<T *>(smem + ((size_t)C::LDS_T * sizeof(T) + 15) / 16 * 16);
     T *ldsS = lds;                          // static values [VS][NP][LD], slot ms at column ms+1
     T *ldsM = lds + VS * NP * LD;           // moving values [V][NP][LD],  slot ms at column ms
     T *ldsF = lds;                          // fluxes [5][NP][LD] (reuses the static region)
-
-    TileCursor cur(a.n_tiles, a.tiles_per_xcd);
-    if (!cur.valid()) return;               // uniform over the workgroup
 
     const int tid = threadIdx.x;
     const int side = tid >= kHalf;          // 0: static, 1: moving (phases 0, 1)
@@ -199,7 +217,7 @@ __global__ __launch_bounds__(kFluxThreads) void k_mortar_flux(FluxArgs<T> a)
     T u[C::ITEMS][NP];
     prefetch<C, T, NP>(a, g, side, lt, u);
 
-    // FP64 matrices for this stage, once per workgroup (scratch in the state region)
+    // FP64 matrices for this stage, once per workgroup and interface
     assemble_matrices<NP, T>(a.basis, a.s, reinterpret_cast<double *>(lds), nullptr, nullptr,
                              mats, mats + 4 * NN);
 
@@ -337,9 +355,84 @@ __global__ __launch_bounds__(kFluxThreads) void k_mortar_flux(FluxArgs<T> a)
                 dst[(size_t)(j + NP * g.pp) * stride] = acc;
             }
         }
-        if (!more) break;
         __syncthreads();   // phase 3 reads the LDS that the next phase 1 overwrites
+        if (!more) break;
         g = gn;
+    }
+}
+
+template <typename T, int NP, bool NSV, bool MET, int RIEM, int BUDGET>
+__global__ __launch_bounds__(kFluxThreads) void k_mortar_flux(FluxArgs<T> a)
+{
+    __shared__ __attribute__((aligned(16))) char smem[flux_smem_bytes<T, NP, NSV, MET, BUDGET>()];
+    TileCursor cur(a.n_tiles);
+    if (!cur.valid()) return;               // uniform over the workgroup
+    run_interface<T, NP, NSV, MET, RIEM, BUDGET>(a, cur, smem);
+}
+
+// ---- several interfaces in one persistent launch ---------------------------------------
+
+constexpr int kMaxBatch = 8;
+
+template <typename T>
+struct BatchArgs {
+    FluxArgs<T> a[kMaxBatch];        // a[i].n_tiles: tiles of interface i
+    int np[kMaxBatch];
+    int met[kMaxBatch];
+    int n_if;
+};
+
+template <int MASK>
+constexpr int mask_max_np()
+{
+    int m = 0;
+    for (int np = 2; np <= kMaxNP; ++np)
+        if (MASK & (1 << np)) m = np;
+    return m;
+}
+
+template <typename T, bool NSV, int BUDGET, int NP>
+constexpr size_t pair_smem()
+{
+    return flux_smem_bytes<T, NP, NSV, false, BUDGET>() > flux_smem_bytes<T, NP, NSV, true, BUDGET>()
+               ? flux_smem_bytes<T, NP, NSV, false, BUDGET>()
+               : flux_smem_bytes<T, NP, NSV, true, BUDGET>();
+}
+
+template <typename T, bool NSV, int BUDGET, int MASK>
+constexpr size_t batch_smem()
+{
+    size_t m = 0;
+#define MORTAR_SMEM_NP(NPV) \
+    if ((MASK & (1 << NPV)) && pair_smem<T, NSV, BUDGET, NPV>() > m) m = pair_smem<T, NSV, BUDGET, NPV>();
+    MORTAR_SMEM_NP(2) MORTAR_SMEM_NP(3) MORTAR_SMEM_NP(4) MORTAR_SMEM_NP(5) MORTAR_SMEM_NP(6)
+    MORTAR_SMEM_NP(7) MORTAR_SMEM_NP(8) MORTAR_SMEM_NP(9) MORTAR_SMEM_NP(10)
+#undef MORTAR_SMEM_NP
+    return m;
+}
+
+// The workgroups take the interfaces one after the other; for each, every XCD gets the
+// same share of its tiles (see TileCursor) and each workgroup assembles that interface's
+// matrices once.  MASK: bit NP set for every degree this instantiation serves; the host
+// only launches it for batches whose degrees are all in MASK.
+template <typename T, bool NSV, int RIEM, int BUDGET, int MASK>
+__global__ __launch_bounds__(kFluxThreads) void k_mortar_flux_batch(BatchArgs<T> b)
+{
+    __shared__ __attribute__((aligned(16))) char smem[batch_smem<T, NSV, BUDGET, MASK>()];
+    for (int i = 0; i < b.n_if; ++i) {
+        TileCursor cur(b.a[i].n_tiles);
+        if (!cur.valid()) continue;          // uniform over the workgroup
+        const bool met = b.met[i] != 0;
+#define MORTAR_BATCH_NP(NPV)                                                             \
+    if ((MASK & (1 << NPV)) && b.np[i] == NPV) {                                         \
+        if (met) run_interface<T, NPV, NSV, true, RIEM, BUDGET>(b.a[i], cur, smem);      \
+        else run_interface<T, NPV, NSV, false, RIEM, BUDGET>(b.a[i], cur, smem);         \
+        continue;                                                                        \
+    }
+        MORTAR_BATCH_NP(2) MORTAR_BATCH_NP(3) MORTAR_BATCH_NP(4) MORTAR_BATCH_NP(5)
+        MORTAR_BATCH_NP(6) MORTAR_BATCH_NP(7) MORTAR_BATCH_NP(8) MORTAR_BATCH_NP(9)
+        MORTAR_BATCH_NP(10)
+#undef MORTAR_BATCH_NP
     }
 }
 

@@ -3,7 +3,7 @@
 
 namespace mortar {
 
-constexpr int kLdsBudget = 49152;   // bytes of LDS per workgroup
+constexpr int kLdsBudget = lds_budget<float>();
 
 template <int NP, bool NSV, bool MET, int RIEM>
 static hipError_t go(const FluxArgs<float> &a, int grid, hipStream_t st)

@@ -3,7 +3,7 @@
 
 namespace mortar {
 
-constexpr int kLdsBudget = 81920;   // bytes of LDS per workgroup
+constexpr int kLdsBudget = lds_budget<double>();
 
 template <int NP, bool NSV, bool MET, int RIEM>
 static hipError_t go(const FluxArgs<double> &a, int grid, hipStream_t st)

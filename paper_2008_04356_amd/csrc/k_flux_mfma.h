@@ -81,7 +81,7 @@ __global__ __launch_bounds__((MCfg<T, NP, NSV, MET>::NT)) void k_mortar_flux_mfm
     T *ldsM = lds + VS * NP * LD;           // moving values [V][NP][LD],  slot ms at column ms
     T *ldsF = lds;                          // fluxes [5][NP][LD]
 
-    TileCursor cur(a.n_tiles, a.tiles_per_xcd);
+    TileCursor cur(a.n_tiles);
     if (!cur.valid()) return;
 
     const int tid = threadIdx.x;

@@ -26,6 +26,12 @@ hipError_t launch_flux_mfma_f32(const FluxArgs<float> &a, int NP, int grid, bool
                                 int riem, hipStream_t st);
 hipError_t launch_flux_mfma_f64(const FluxArgs<double> &a, int NP, int grid, bool ns, bool met,
                                 int riem, hipStream_t st);
+hipError_t launch_flux_batch_f32(const BatchArgs<float> &b, int grid, bool ns, int riem,
+                                 bool turbine, hipStream_t st);
+hipError_t launch_flux_batch_f64(const BatchArgs<double> &b, int grid, bool ns, int riem,
+                                 bool turbine, hipStream_t st);
+int flux_batch_occupancy_f32(bool ns, int riem, bool turbine);
+int flux_batch_occupancy_f64(bool ns, int riem, bool turbine);
 
 // ------------------------------------------------------------------------------------
 // FP64 node sets by bracketing and bisection (roots of P_NP for Gauss, of P_N' for
@@ -370,9 +376,25 @@ static int apply_update(Handle *h, const int64_t *n, const double *s, hipStream_
 
 }  // namespace mortar
 
+namespace mortar {
+template <typename T>
+void fill_args(const Iface &f, const void *Us, const void *Um, const void *Gs, const void *Gm,
+               void *Fs, void *Fm, FluxArgs<T> &a, int &n_tiles);
+}  // namespace mortar
+
 using namespace mortar;
 
 struct mortar_handle : public mortar::Handle {};
+
+// A captured stage: the flux launch(es) of a handle for fixed buffers.
+struct mortar_graph {
+    mortar_handle *h = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<hipGraphNode_t> nodes;       // kernel nodes in launch order
+    std::vector<const void *> Us, Um, Gs, Gm;
+    std::vector<void *> Fs, Fm;
+};
 
 extern "C" {
 
@@ -445,6 +467,24 @@ int mortar_setup(const mortar_iface_desc *desc, int n_iface, mortar_handle **out
             return rc;
         }
     }
+    // One persistent launch for every interface when they share element type, physics and
+    // flux (and use the VALU-projection kernel).
+    if (n_iface > 1 && n_iface <= kMaxBatch) {
+        const Iface &f0 = h->ifs[0];
+        bool same = true, turbine = true;
+        for (const Iface &f : h->ifs) {
+            same = same && f.elem == f0.elem && f.d.physics == f0.d.physics &&
+                   f.d.riemann == f0.d.riemann && f.flux_variant == 0;
+            turbine = turbine && (f.NP == 4 || f.NP == 6 || f.NP == 8);
+        }
+        const bool ns = f0.d.physics == MORTAR_NAVIER_STOKES;
+        const int riem = f0.d.riemann == MORTAR_FLUX_ROE;
+        h->batched = same;
+        h->batch_turbine = turbine && ns && riem && f0.elem == 4;
+        if (same)
+            h->batch_occ = f0.elem == 8 ? flux_batch_occupancy_f64(ns, riem, h->batch_turbine)
+                                        : flux_batch_occupancy_f32(ns, riem, h->batch_turbine);
+    }
     *out = h;
     return MORTAR_OK;
 }
@@ -492,6 +532,14 @@ int mortar_flux(mortar_handle *h, const void *const *U_s, const void *const *U_m
         const bool ns = f.d.physics == MORTAR_NAVIER_STOKES;
         if (!U_s[i] || !U_m[i] || !F_s[i] || !F_m[i]) return MORTAR_ERR_INVALID_ARG;
         if (ns && (!G_s || !G_m || !G_s[i] || !G_m[i])) return MORTAR_ERR_INVALID_ARG;
+    }
+    if (h->batched) {
+        TRY_HIP(launch_flux_batched(*h, U_s, U_m, G_s, G_m, F_s, F_m, st));
+        return MORTAR_OK;
+    }
+    for (size_t i = 0; i < h->ifs.size(); ++i) {
+        const Iface &f = h->ifs[i];
+        const bool ns = f.d.physics == MORTAR_NAVIER_STOKES;
         TRY_HIP(launch_flux(f, h->n_cu, U_s[i], U_m[i], ns ? G_s[i] : nullptr,
                             ns ? G_m[i] : nullptr, F_s[i], F_m[i], st));
     }
@@ -559,9 +607,173 @@ int mortar_conservation(mortar_handle *h, const void *const *F_s, const void *co
     return rc;
 }
 
+int mortar_graph_create(mortar_handle *h, const void *const *U_s, const void *const *U_m,
+                        const void *const *G_s, const void *const *G_m, void *const *F_s,
+                        void *const *F_m, mortar_graph **out)
+{
+    if (!h || !out || !U_s || !U_m || !F_s || !F_m) return MORTAR_ERR_INVALID_ARG;
+    const size_t n_if = h->ifs.size();
+    mortar_graph *g = new (std::nothrow) mortar_graph();
+    if (!g) return MORTAR_ERR_OOM;
+    g->h = h;
+    for (size_t i = 0; i < n_if; ++i) {
+        g->Us.push_back(U_s[i]);
+        g->Um.push_back(U_m[i]);
+        g->Gs.push_back(G_s ? G_s[i] : nullptr);
+        g->Gm.push_back(G_m ? G_m[i] : nullptr);
+        g->Fs.push_back(F_s[i]);
+        g->Fm.push_back(F_m[i]);
+    }
+    hipStream_t cs = nullptr;
+    int rc = MORTAR_OK;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) rc = MORTAR_ERR_HIP;
+    if (rc == MORTAR_OK && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        rc = MORTAR_ERR_HIP;
+    if (rc == MORTAR_OK) {
+        const int frc = mortar_flux(h, g->Us.data(), g->Um.data(), g->Gs.data(), g->Gm.data(),
+                                    g->Fs.data(), g->Fm.data(), cs);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(cs, &graph);
+        g->graph = graph;
+        if (frc != MORTAR_OK) rc = frc;
+        else if (e != hipSuccess || !graph) rc = MORTAR_ERR_HIP;
+    }
+    if (rc == MORTAR_OK) {
+        size_t nn = 0;
+        if (hipGraphGetNodes(g->graph, nullptr, &nn) != hipSuccess) rc = MORTAR_ERR_HIP;
+        std::vector<hipGraphNode_t> all(nn);
+        if (rc == MORTAR_OK && nn && hipGraphGetNodes(g->graph, all.data(), &nn) != hipSuccess)
+            rc = MORTAR_ERR_HIP;
+        for (size_t i = 0; rc == MORTAR_OK && i < nn; ++i) {
+            hipGraphNodeType t;
+            if (hipGraphNodeGetType(all[i], &t) != hipSuccess) rc = MORTAR_ERR_HIP;
+            else if (t == hipGraphNodeTypeKernel) g->nodes.push_back(all[i]);
+        }
+        const size_t want = h->batched ? 1 : n_if;
+        if (rc == MORTAR_OK && g->nodes.size() != want) rc = MORTAR_ERR_UNSUPPORTED;
+    }
+    if (rc == MORTAR_OK && hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess)
+        rc = MORTAR_ERR_HIP;
+    if (cs) (void)hipStreamDestroy(cs);
+    if (rc != MORTAR_OK) {
+        mortar_graph_destroy(g);
+        return rc;
+    }
+    *out = g;
+    return MORTAR_OK;
+}
+
+}  // extern "C"
+
+template <typename Args>
+static int set_node_args(mortar_graph *g, size_t node, Args &args)
+{
+    hipKernelNodeParams p;
+    if (hipGraphKernelNodeGetParams(g->nodes[node], &p) != hipSuccess) return MORTAR_ERR_HIP;
+    void *kp[1] = {&args};
+    p.kernelParams = kp;
+    p.extra = nullptr;
+    if (hipGraphExecKernelNodeSetParams(g->exec, g->nodes[node], &p) != hipSuccess)
+        return MORTAR_ERR_HIP;
+    return MORTAR_OK;
+}
+
+extern "C" {
+
+int mortar_graph_launch(mortar_graph *g, const double *disp, void *stream)
+{
+    if (!g || !g->exec || !disp) return MORTAR_ERR_INVALID_ARG;
+    mortar_handle *h = g->h;
+    int rc = mortar_update_displacement(h, disp, stream);
+    if (rc) return rc;
+    const size_t n_if = h->ifs.size();
+    if (h->batched) {
+        const bool f64 = h->ifs[0].elem == 8;
+        auto build = [&](auto &b) {
+            b.n_if = (int)n_if;
+            for (size_t i = 0; i < n_if; ++i) {
+                int nt = 0;
+                fill_args(h->ifs[i], g->Us[i], g->Um[i], g->Gs[i], g->Gm[i], g->Fs[i], g->Fm[i],
+                          b.a[i], nt);
+                b.np[i] = h->ifs[i].NP;
+                b.met[i] = h->ifs[i].d_metrics != nullptr;
+            }
+        };
+        if (f64) {
+            BatchArgs<double> b;
+            build(b);
+            rc = set_node_args(g, 0, b);
+        } else {
+            BatchArgs<float> b;
+            build(b);
+            rc = set_node_args(g, 0, b);
+        }
+    } else {
+        for (size_t i = 0; i < n_if && rc == MORTAR_OK; ++i) {
+            int nt = 0;
+            if (h->ifs[i].elem == 8) {
+                FluxArgs<double> a;
+                fill_args(h->ifs[i], g->Us[i], g->Um[i], g->Gs[i], g->Gm[i], g->Fs[i], g->Fm[i], a, nt);
+                rc = set_node_args(g, i, a);
+            } else {
+                FluxArgs<float> a;
+                fill_args(h->ifs[i], g->Us[i], g->Um[i], g->Gs[i], g->Gm[i], g->Fs[i], g->Fm[i], a, nt);
+                rc = set_node_args(g, i, a);
+            }
+        }
+    }
+    if (rc) return rc;
+    TRY_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    return MORTAR_OK;
+}
+
+int mortar_graph_destroy(mortar_graph *g)
+{
+    if (!g) return MORTAR_ERR_INVALID_ARG;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return MORTAR_OK;
+}
+
 }  // extern "C"
 
 namespace mortar {
+
+// Kernel arguments of one interface for the VALU or matrix-core kernel.
+template <typename T>
+void fill_args(const Iface &f, const void *Us, const void *Um, const void *Gs,
+                      const void *Gm, void *Fs, void *Fm, FluxArgs<T> &a, int &n_tiles)
+{
+    const bool ns = f.d.physics == MORTAR_NAVIER_STOKES;
+    const bool met = f.d_metrics != nullptr;
+    const double gm1 = f.d.gamma - 1.0;
+    const double kfac = ns ? f.d.mu * f.d.gamma / (gm1 * f.d.Pr) : 0.0;
+    const int64_t np = f.d.n_par;
+    const int cap = f.flux_variant == 1 ? 15
+                  : (f.elem == 8 ? flux_tile_capacity_f64(f.NP, ns, met)
+                                 : flux_tile_capacity_f32(f.NP, ns, met));
+    // balanced tiles: as few as the capacity allows, all of nearly equal length
+    const int tiles_per_row = (f.d.n_par + cap - 1) / cap;
+    const int tile_len = (f.d.n_par + tiles_per_row - 1) / tiles_per_row;
+    n_tiles = tiles_per_row * f.NP * f.d.n_perp;
+    a.Us = (const T *)Us; a.Um = (const T *)Um;
+    a.Gs = (const T *)Gs; a.Gm = (const T *)Gm;
+    a.met = (const T *)f.d_metrics;
+    a.Fs = (T *)Fs; a.Fm = (T *)Fm;
+    a.fid_s = f.d_fid_s; a.fid_m = f.d_fid_m;
+    a.basis = f.d_basis;
+    a.s = f.s;
+    a.nmod = (int)(((f.n % np) + np) % np);
+    a.n_par = f.d.n_par; a.n_perp = f.d.n_perp;
+    a.nfs = f.d.n_face_static; a.nfm = f.d.n_face_moving;
+    a.tiles_per_row = tiles_per_row;
+    a.tile_len = tile_len;
+    a.n_tiles = n_tiles;
+    a.nx = (T)f.d.normal[0]; a.ny = (T)f.d.normal[1]; a.nz = (T)f.d.normal[2];
+    a.dS = (T)f.d.dS;
+    a.gas = {(T)gm1, (T)f.d.gamma, (T)(ns ? f.d.mu : 0.0), (T)kfac};
+}
 
 hipError_t launch_flux(const Iface &f, int n_cu, const void *Us, const void *Um, const void *Gs,
                        const void *Gm, void *Fs, void *Fm, hipStream_t st)
@@ -569,49 +781,51 @@ hipError_t launch_flux(const Iface &f, int n_cu, const void *Us, const void *Um,
     const bool ns = f.d.physics == MORTAR_NAVIER_STOKES;
     const bool met = f.d_metrics != nullptr;
     const int riem = f.d.riemann == MORTAR_FLUX_ROE ? 1 : 0;
-    const double gm1 = f.d.gamma - 1.0;
-    const double kfac = ns ? f.d.mu * f.d.gamma / (gm1 * f.d.Pr) : 0.0;
-    const int64_t np = f.d.n_par;
-    const int nmod = (int)(((f.n % np) + np) % np);
-    const int cap = f.flux_variant == 1 ? 15
-                  : (f.elem == 8 ? flux_tile_capacity_f64(f.NP, ns, met)
-                                 : flux_tile_capacity_f32(f.NP, ns, met));
-    if (cap <= 0) return hipErrorInvalidValue;
-    // balanced tiles: as few as the capacity allows, all of nearly equal length
-    const int tiles_per_row = (f.d.n_par + cap - 1) / cap;
-    const int tile_len = (f.d.n_par + tiles_per_row - 1) / tiles_per_row;
-    const int n_tiles = tiles_per_row * f.NP * f.d.n_perp;
-    const int grid = std::max(1, std::min(n_tiles, f.flux_occ * n_cu));
-    auto fill = [&](auto &a, auto zero) {
-        using T = decltype(zero);
-        a.Us = (const T *)Us; a.Um = (const T *)Um;
-        a.Gs = (const T *)Gs; a.Gm = (const T *)Gm;
-        a.met = (const T *)f.d_metrics;
-        a.Fs = (T *)Fs; a.Fm = (T *)Fm;
-        a.fid_s = f.d_fid_s; a.fid_m = f.d_fid_m;
-        a.basis = f.d_basis;
-        a.s = f.s;
-        a.nmod = nmod;
-        a.n_par = f.d.n_par; a.n_perp = f.d.n_perp;
-        a.nfs = f.d.n_face_static; a.nfm = f.d.n_face_moving;
-        a.tiles_per_row = tiles_per_row;
-        a.tile_len = tile_len;
-        a.n_tiles = n_tiles;
-        a.tiles_per_xcd = (n_tiles + kXcds - 1) / kXcds;
-        a.nx = (T)f.d.normal[0]; a.ny = (T)f.d.normal[1]; a.nz = (T)f.d.normal[2];
-        a.dS = (T)f.d.dS;
-        a.gas = {(T)gm1, (T)f.d.gamma, (T)(ns ? f.d.mu : 0.0), (T)kfac};
-    };
+    int n_tiles = 0;
     if (f.elem == 8) {
         FluxArgs<double> a;
-        fill(a, 0.0);
+        fill_args(f, Us, Um, Gs, Gm, Fs, Fm, a, n_tiles);
+        const int grid = std::max(1, std::min(n_tiles, f.flux_occ * n_cu));
         return f.flux_variant == 1 ? launch_flux_mfma_f64(a, f.NP, grid, ns, met, riem, st)
                                    : launch_flux_f64(a, f.NP, grid, ns, met, riem, st);
     }
     FluxArgs<float> a;
-    fill(a, 0.0f);
+    fill_args(f, Us, Um, Gs, Gm, Fs, Fm, a, n_tiles);
+    const int grid = std::max(1, std::min(n_tiles, f.flux_occ * n_cu));
     return f.flux_variant == 1 ? launch_flux_mfma_f32(a, f.NP, grid, ns, met, riem, st)
                                : launch_flux_f32(a, f.NP, grid, ns, met, riem, st);
+}
+
+hipError_t launch_flux_batched(const Handle &h, const void *const *Us, const void *const *Um,
+                               const void *const *Gs, const void *const *Gm, void *const *Fs,
+                               void *const *Fm, hipStream_t st)
+{
+    const Iface &f0 = h.ifs[0];
+    const bool ns = f0.d.physics == MORTAR_NAVIER_STOKES;
+    const int riem = f0.d.riemann == MORTAR_FLUX_ROE ? 1 : 0;
+    int total = 0;
+    auto build = [&](auto &b) {
+        b.n_if = (int)h.ifs.size();
+        for (int i = 0; i < b.n_if; ++i) {
+            const Iface &f = h.ifs[i];
+            int nt = 0;
+            fill_args(f, Us[i], Um[i], ns ? Gs[i] : nullptr, ns ? Gm[i] : nullptr, Fs[i], Fm[i],
+                      b.a[i], nt);
+            b.np[i] = f.NP;
+            b.met[i] = f.d_metrics != nullptr;
+            total += nt;
+        }
+    };
+    if (f0.elem == 8) {
+        BatchArgs<double> b;
+        build(b);
+        const int grid = std::max(1, std::min(total, h.batch_occ * h.n_cu));
+        return launch_flux_batch_f64(b, grid, ns, riem, h.batch_turbine, st);
+    }
+    BatchArgs<float> b;
+    build(b);
+    const int grid = std::max(1, std::min(total, h.batch_occ * h.n_cu));
+    return launch_flux_batch_f32(b, grid, ns, riem, h.batch_turbine, st);
 }
 
 }  // namespace mortar

@@ -76,6 +76,9 @@ struct Iface {
 struct Handle {
     int device = 0;
     int n_cu = 256;
+    bool batched = false;              // all interfaces go in one persistent launch
+    bool batch_turbine = false;        // the N = 3, 5, 7 instantiation covers the batch
+    int batch_occ = 1;
     std::vector<Iface> ifs;
 };
 
@@ -84,6 +87,10 @@ hipError_t launch_assemble(const Iface &f, hipStream_t st);
 hipError_t launch_index_map(Iface &f, int side, hipStream_t st);
 hipError_t launch_flux(const Iface &f, int n_cu, const void *Us, const void *Um, const void *Gs,
                        const void *Gm, void *Fs, void *Fm, hipStream_t st);
+struct Handle;
+hipError_t launch_flux_batched(const Handle &h, const void *const *Us, const void *const *Um,
+                               const void *const *Gs, const void *const *Gm, void *const *Fs,
+                               void *const *Fm, hipStream_t st);
 hipError_t launch_conservation(const Iface &f, const void *Fs, const void *Fm, double *d_out,
                                hipStream_t st);
 

@@ -65,6 +65,10 @@ def _load():
     L.mortar_get_index_map.argtypes = [C.c_void_p, C.c_int, C.c_int, _ip, _ip]
     L.mortar_get_projection.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
     L.mortar_conservation.argtypes = [C.c_void_p, _vpp, _vpp, _dp, C.c_void_p]
+    L.mortar_graph_create.argtypes = [C.c_void_p, _vpp, _vpp, _vpp, _vpp, _vpp, _vpp,
+                                      C.POINTER(C.c_void_p)]
+    L.mortar_graph_launch.argtypes = [C.c_void_p, _dp, C.c_void_p]
+    L.mortar_graph_destroy.argtypes = [C.c_void_p]
     return L
 
 
@@ -111,6 +115,22 @@ def mortar_flux(h, Us, Um, Gs, Gm, Fs, Fm, stream: int = 0) -> int:
     """Each argument: a sequence of device addresses (ints) or None entries."""
     return lib.mortar_flux(h, _ptrs(Us), _ptrs(Um), _ptrs(Gs), _ptrs(Gm), _ptrs(Fs), _ptrs(Fm),
                            C.c_void_p(stream))
+
+
+def mortar_graph_create(h, Us, Um, Gs, Gm, Fs, Fm):
+    g = C.c_void_p()
+    _check(lib.mortar_graph_create(h, _ptrs(Us), _ptrs(Um), _ptrs(Gs), _ptrs(Gm), _ptrs(Fs),
+                                   _ptrs(Fm), C.byref(g)), "mortar_graph_create")
+    return g
+
+
+def mortar_graph_launch(g, disp: Sequence[float], stream: int = 0) -> int:
+    d = (C.c_double * len(disp))(*[float(x) for x in disp])
+    return lib.mortar_graph_launch(g, d, C.c_void_p(stream))
+
+
+def mortar_graph_destroy(g) -> int:
+    return lib.mortar_graph_destroy(g)
 
 
 def mortar_destroy(h) -> int:
@@ -244,9 +264,39 @@ class MortarOperator:
                                          Pb.ctypes.data_as(_dp)), "mortar_get_projection")
         return Pf, Pb
 
+    def graph(self, Us, Um, Gs, Gm, Fs, Fm):
+        """Captures one stage for these fixed buffers; see MortarGraph."""
+        return MortarGraph(self, Us, Um, Gs, Gm, Fs, Fm)
+
     def conservation(self, Fs, Fm, stream=None):
         out = np.zeros((len(self.specs), 5, 3))
         p = lambda ts: _ptrs([t.data_ptr() for t in ts])  # noqa: E731
         _check(lib.mortar_conservation(self.h, p(Fs), p(Fm), out.ctypes.data_as(_dp),
                                        C.c_void_p(self._stream(stream))), "mortar_conservation")
         return out
+
+
+class MortarGraph:
+    """One stage of an operator captured as a HIP graph for fixed face buffers; each
+    launch(disp) updates the displacement and replays the graph."""
+
+    def __init__(self, op, Us, Um, Gs, Gm, Fs, Fm):
+        p = lambda ts: None if ts is None else [None if t is None else t.data_ptr() for t in ts]  # noqa: E731
+        self.op = op
+        self._keep = (Us, Um, Gs, Gm, Fs, Fm)
+        self.g = mortar_graph_create(op.h, p(Us), p(Um), p(Gs), p(Gm), p(Fs), p(Fm))
+
+    def launch(self, disp, stream=None):
+        _check(mortar_graph_launch(self.g, disp, MortarOperator._stream(stream)),
+               "mortar_graph_launch")
+
+    def close(self):
+        if self.g:
+            _check(mortar_graph_destroy(self.g), "mortar_graph_destroy")
+            self.g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
