@@ -35,6 +35,8 @@ def parse():
     p.add_argument("--cpu-stages", type=int, default=10)
     p.add_argument("--rotate-bytes", type=float, default=1.2e9)
     p.add_argument("--graph", action="store_true", help="replay a captured HIP graph per stage")
+    p.add_argument("--precision", choices=("fp32", "bf16", "fp16"), default="fp32",
+                   help="headline leg: FP32, or FP32 data with bf16 / fp16 projection GEMMs")
     p.add_argument("--copy-calibration", type=float, default=0.0,
                    help="only run a plain device copy of this many MB (counter calibration)")
     return p.parse_args()
@@ -219,7 +221,8 @@ def main():
     from paper_2008_04356_amd import workloads as W
 
     torch.cuda.set_device(0)
-    specs32, disp = W.config(a.config, precision=W.FP32)
+    prec = {"fp32": W.FP32, "bf16": W.BF16_MFMA, "fp16": W.FP16_MFMA}[a.precision]
+    specs32, disp = W.config(a.config, precision=prec)
     r32 = run_leg(M, W, specs32, disp, a.steps, a.warmup, a.rotate_bytes, graph=a.graph)
     r64 = None
     if not a.no_fp64:
@@ -253,7 +256,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": {"fp32": "f32", "bf16": "f32 data, bf16 GEMM operands",
+                  "fp16": "f32 data, f16 GEMM operands"}[a.precision],
         "data": "synthetic",
         "config": {"workload": names.get(a.config, f"config {a.config}"),
                    "mortar_points_per_step": sum(s.mortar_points for s in specs32),

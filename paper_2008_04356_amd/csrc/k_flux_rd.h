@@ -1,0 +1,665 @@
+// Register-direct mortar-flux kernel: one wave per tile, both projections on the matrix
+// cores, the pointwise fluxes computed straight from the matrix-core results.
+//
+// Operator: Sec. 3.3 steps 3-5 with the operators of Sec. 3.2, the same tile chain as the
+// other flux kernels (k_flux.h).  A tile is 16 face slots of one line:
+//   static slot f = face i0-1+f (slot 0 is the halo face),
+//   moving slot f = face i0+f-n-1.
+// Column f of the forward GEMM holds the two mortars (i0-1+f, 0) (rows 0..NP-1, node q)
+// and (i0-1+f, 1) (rows NP..2NP-1).  On the static side these are the two sub-intervals
+// of static slot f (matrices Pf0, Pf1).  On the moving side mortar (i0-1+f, 0) is the
+// upper part of moving slot f-1 (Pf2) and (i0-1+f, 1) the lower part of moving slot f
+// (Pf3), so the moving GEMM takes K = 2 NP: the first NP from the face data of slot f-1,
+// brought over by a one-lane DPP shift inside each row of 16 lanes, the second NP from
+// slot f itself.  With the matrix-core result layout every lane then holds both sides'
+// values of the same mortar nodes for every variable and evaluates their Riemann + BR1
+// fluxes in registers.  The back projection is a GEMM with K = the 2 NP mortar nodes of
+// a column, whose B operand is exactly those flux registers (one more DPP shift for the
+// moving side, whose upper mortar sits in the next column).  Nothing goes through LDS
+// after the prologue, and the waves of a workgroup never wait for each other.
+//
+// Precision (PREC): 0 runs the GEMMs in the element type (v_mfma_{f32,f64}_16x16x4).
+// 1 / 2 round the GEMM operands to bf16 / fp16 (v_mfma_f32_16x16x16_{bf16,f16}, FP32
+// accumulation; FP32 data).  The rounded matrices no longer integrate exactly, so the
+// back projection is then corrected per face line: with T the integral of the line's
+// mortar fluxes (sum of J_k w_q F, FP64 accumulation of FP32 fluxes) and A the integral
+// of the projected face flux (sum of w_j F_j), (T - A) / sum(w) is added to every node
+// of the line.  This restores the line-by-line equality of the static and moving
+// integrals (discrete conservation, Sec. 3.2) up to FP32 storage rounding.
+#pragma once
+
+#include "assemble.h"
+#include "flux_physics.h"
+#include "k_flux.h"
+#include "mortar_internal.h"
+
+namespace mortar {
+
+typedef float rd_v4f __attribute__((ext_vector_type(4)));
+typedef double rd_v4d __attribute__((ext_vector_type(4)));
+typedef __bf16 rd_v4bf __attribute__((ext_vector_type(4)));
+typedef _Float16 rd_v4h __attribute__((ext_vector_type(4)));
+
+// Matrix-core operation of a precision mode.  Operand layouts: 16x16x4 (E = 1) lane l
+// supplies A[l % 16][l / 16] and B[l / 16][l % 16]; 16x16x16 (E = 4) lane l supplies
+// A[l % 16][4 (l / 16) + e] and B[4 (l / 16) + e][l % 16], e = 0..3.  Result: lane l,
+// register r holds D[row(l / 16, r)][l % 16].
+template <typename T, int PREC> struct RdOp;
+template <> struct RdOp<float, 0> {
+    static constexpr int E = 1, KW = 4;
+    using op_t = float;
+    using acc_t = rd_v4f;
+    __device__ static __forceinline__ op_t pack(const float *v) { return v[0]; }
+    __device__ static __forceinline__ acc_t mma(op_t a, op_t b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static __forceinline__ int row(int kq, int r) { return 4 * kq + r; }
+};
+template <> struct RdOp<double, 0> {
+    static constexpr int E = 1, KW = 4;
+    using op_t = double;
+    using acc_t = rd_v4d;
+    __device__ static __forceinline__ op_t pack(const double *v) { return v[0]; }
+    __device__ static __forceinline__ acc_t mma(op_t a, op_t b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static __forceinline__ int row(int kq, int r) { return kq + 4 * r; }
+};
+template <> struct RdOp<float, 1> {
+    static constexpr int E = 4, KW = 16;
+    using op_t = rd_v4bf;
+    using acc_t = rd_v4f;
+    __device__ static __forceinline__ op_t pack(const float *v)
+    {
+        op_t r;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) r[e] = (__bf16)v[e];
+        return r;
+    }
+    __device__ static __forceinline__ acc_t mma(op_t a, op_t b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+    }
+    __device__ static __forceinline__ int row(int kq, int r) { return 4 * kq + r; }
+};
+template <> struct RdOp<float, 2> {
+    static constexpr int E = 4, KW = 16;
+    using op_t = rd_v4h;
+    using acc_t = rd_v4f;
+    __device__ static __forceinline__ op_t pack(const float *v)
+    {
+        op_t r;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) r[e] = (_Float16)v[e];
+        return r;
+    }
+    __device__ static __forceinline__ acc_t mma(op_t a, op_t b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+    }
+    __device__ static __forceinline__ int row(int kq, int r) { return 4 * kq + r; }
+};
+
+template <int NP, bool NSV, bool MET, int KW>
+struct RdCfg {
+    static constexpr int V = NSV ? 20 : 5;                 // projected per side
+    static constexpr int VS = V + (MET ? 4 : 0);           // static side adds the metrics
+    static constexpr int NN = NP * NP;
+    static constexpr int RB = (2 * NP + 15) / 16;          // 16-row blocks of mortar nodes
+    static constexpr int KSF = (NP + KW - 1) / KW;         // static forward K steps
+    static constexpr int KSM = (2 * NP + KW - 1) / KW;     // moving forward K steps
+    static constexpr int KSB = RB * 16 / KW;               // backward K steps
+    static constexpr int WAVES = 4;                        // independent waves per workgroup
+    static constexpr int NT = 64 * WAVES;
+};
+
+// Output faces per tile of the register-direct kernel (16 slots, one is the halo).
+constexpr int kRdTileFaces = 15;
+
+// Value of lane - 1 (rd_left) or lane + 1 (rd_right) within each row of 16 lanes; the
+// lane at the row's edge receives 0.
+__device__ __forceinline__ int rd_shift_left(int x)
+{
+    return __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, true);   // row_shr:1
+}
+__device__ __forceinline__ int rd_shift_right(int x)
+{
+    return __builtin_amdgcn_update_dpp(0, x, 0x101, 0xF, 0xF, true);   // row_shl:1
+}
+__device__ __forceinline__ float rd_left(float x) { return __int_as_float(rd_shift_left(__float_as_int(x))); }
+__device__ __forceinline__ float rd_right(float x) { return __int_as_float(rd_shift_right(__float_as_int(x))); }
+__device__ __forceinline__ double rd_left(double x)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = (unsigned)rd_shift_left((int)(unsigned)b);
+    const unsigned hi = (unsigned)rd_shift_left((int)(unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double rd_right(double x)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = (unsigned)rd_shift_right((int)(unsigned)b);
+    const unsigned hi = (unsigned)rd_shift_right((int)(unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Buffer access (bit patterns, no conversion) with a 32-bit per-lane byte offset and a scalar byte offset (the
+// variable's plane).  Word 3 of the descriptor: 32-bit data format, no swizzle, raw
+// addressing; accesses at or beyond num_records bytes read 0 and write nothing.
+typedef __amdgpu_buffer_rsrc_t rd_rsrc_t;
+__device__ __forceinline__ rd_rsrc_t rd_rsrc(const void *p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T> __device__ __forceinline__ T rd_load(const rd_rsrc_t &r, uint32_t off, int soff);
+template <> __device__ __forceinline__ float rd_load<float>(const rd_rsrc_t &r, uint32_t off, int soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, soff, 0));
+}
+template <> __device__ __forceinline__ double rd_load<double>(const rd_rsrc_t &r, uint32_t off, int soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, soff, 0));
+}
+typedef unsigned rd_u2 __attribute__((ext_vector_type(2)));
+template <typename T> __device__ __forceinline__ void rd_store(T x, const rd_rsrc_t &r, uint32_t off, int soff);
+template <> __device__ __forceinline__ void rd_store<float>(float x, const rd_rsrc_t &r, uint32_t off, int soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, (int)off, soff, 0);
+}
+template <> __device__ __forceinline__ void rd_store<double>(double x, const rd_rsrc_t &r, uint32_t off, int soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(rd_u2, x), r, (int)off, soff, 0);
+}
+
+// Persistent schedule at wave granularity, with the XCD split of TileCursor: XCD x owns
+// the contiguous eighth of the tiles, and the waves of the workgroups on that XCD take
+// them in turn.  Requires gridDim.x >= min(8, n) so that every XCD's share has workers.
+struct WaveCursor {
+    int k, limit, stride;
+    __device__ WaveCursor(int n, int waves, int wave)
+    {
+        const int g = gridDim.x;
+        const int xcd = blockIdx.x % kXcds;
+        stride = (g / kXcds + ((g % kXcds) > xcd ? 1 : 0)) * waves;
+        const int per = (n + kXcds - 1) / kXcds;
+        const int base = xcd * per;
+        limit = min(n, base + per);
+        k = base + (blockIdx.x / kXcds) * waves + wave;
+    }
+    __device__ bool valid() const { return k < limit; }
+    __device__ int tile() const { return k; }
+    __device__ void next() { k += stride; }
+};
+
+template <typename T, int NP, bool NSV, bool MET, int RIEM, int PREC>
+__global__ __launch_bounds__(256) void k_mortar_flux_rd(FluxArgs<T> a)
+{
+    using Op = RdOp<T, PREC>;
+    using C = RdCfg<NP, NSV, MET, Op::KW>;
+    using op_t = typename Op::op_t;
+    using acc_t = typename Op::acc_t;
+    constexpr int V = C::V, VS = C::VS, NN = C::NN, RB = C::RB, E = Op::E, KW = Op::KW;
+    constexpr int KSF = C::KSF, KSM = C::KSM, KSB = C::KSB, P = NN;
+    constexpr int LF = KSF * E, LM = KSM * E;              // loaded values per lane and var
+    static_assert(C::NT == 256, "launch bounds");
+    static_assert(NP <= 16, "one 16-row block of face nodes in the back projection");
+
+    __shared__ double work[8 * NN];
+    __shared__ T mats[8 * NN];               // Pf[4][NP][NP], Pb[4][NP][NP]
+    __shared__ double wq[NP];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int col = lane & 15;               // slot of this lane
+    const int kq = lane >> 4;                // operand K group / result row group
+
+    assemble_matrices<NP, T>(a.basis, a.s, work, nullptr, nullptr, mats, mats + 4 * NN);
+    if (tid < NP) wq[tid] = a.basis->w[tid];
+    __syncthreads();
+
+    auto kidx = [&](int ks, int e) { return ks * KW + (E == 1 ? kq : 4 * kq + e); };
+
+    // ---- A operands, kept in registers for the whole launch ----------------------------
+    op_t Afs[RB][KSF], Afm[RB][KSM], Abs[KSB], Abm[KSB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+        const int row = 16 * rb + col;       // A row of this lane
+#pragma unroll
+        for (int ks = 0; ks < KSF; ++ks) {
+            T x[4] = {0, 0, 0, 0};
+            float f[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int j = kidx(ks, e);
+                if (j < NP && row < NP) x[e] = mats[0 * NN + row * NP + j];
+                if (j < NP && row >= NP && row < 2 * NP) x[e] = mats[1 * NN + (row - NP) * NP + j];
+                f[e] = (float)x[e];
+            }
+            if constexpr (PREC == 0) Afs[rb][ks] = Op::pack(x);
+            else Afs[rb][ks] = Op::pack(f);
+        }
+#pragma unroll
+        for (int ks = 0; ks < KSM; ++ks) {
+            T x[4] = {0, 0, 0, 0};
+            float f[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int k = kidx(ks, e);
+                if (k < NP && row < NP) x[e] = mats[2 * NN + row * NP + k];
+                if (k >= NP && k < 2 * NP && row >= NP && row < 2 * NP)
+                    x[e] = mats[3 * NN + (row - NP) * NP + (k - NP)];
+                f[e] = (float)x[e];
+            }
+            if constexpr (PREC == 0) Afm[rb][ks] = Op::pack(x);
+            else Afm[rb][ks] = Op::pack(f);
+        }
+    }
+    // back projection: A[j = col][rho], rho = mortar-node row supplied in K step kb
+    auto bsrc = [&](int kb, int e, int &rb, int &r) {
+        rb = E == 1 ? kb / 4 : kb;
+        r = E == 1 ? kb % 4 : e;
+    };
+#pragma unroll
+    for (int kb = 0; kb < KSB; ++kb) {
+        T xs[4] = {0, 0, 0, 0}, xm[4] = {0, 0, 0, 0};
+        float fs[4] = {0, 0, 0, 0}, fm[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            int rb, r;
+            bsrc(kb, e, rb, r);
+            const int rho = 16 * rb + Op::row(kq, r);
+            if (col < NP && rho < 2 * NP) {
+                const int k = rho < NP ? 0 : 1;
+                const int q = rho - k * NP;
+                xs[e] = mats[4 * NN + k * NN + col * NP + q];
+                xm[e] = mats[4 * NN + (2 + k) * NN + col * NP + q];
+            }
+            fs[e] = (float)xs[e];
+            fm[e] = (float)xm[e];
+        }
+        if constexpr (PREC == 0) {
+            Abs[kb] = Op::pack(xs);
+            Abm[kb] = Op::pack(xm);
+        } else {
+            Abs[kb] = Op::pack(fs);
+            Abm[kb] = Op::pack(fm);
+        }
+    }
+    // mortar-node rows of this lane and their quadrature weights J_k w_q (the same on
+    // both sides: J = s for mortar (., 0) = moving upper part, 1 - s for (., 1))
+    int rrow[RB][4];
+    double cw[RB][4];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int rho = 16 * rb + Op::row(kq, r);
+            rrow[rb][r] = rho;
+            cw[rb][r] = rho < NP ? a.s * wq[rho] : (rho < 2 * NP ? (1.0 - a.s) * wq[rho - NP] : 0.0);
+        }
+    double wj[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int j = Op::row(kq, r);
+        wj[r] = j < NP ? wq[j] : 0.0;
+    }
+
+    const int np_ = a.n_par;
+    const int nmod = a.nmod;
+    // buffer resources of the arrays (each below 4 GiB; the host checks this)
+    const int pbytes_s = (int)((size_t)P * a.nfs * sizeof(T));
+    const int pbytes_m = (int)((size_t)P * a.nfm * sizeof(T));
+    const rd_rsrc_t rU_s = rd_rsrc(a.Us, 5u * (uint32_t)pbytes_s);
+    const rd_rsrc_t rU_m = rd_rsrc(a.Um, 5u * (uint32_t)pbytes_m);
+    const rd_rsrc_t rG_s = rd_rsrc(a.Gs, NSV ? 15u * (uint32_t)pbytes_s : 0u);
+    const rd_rsrc_t rG_m = rd_rsrc(a.Gm, NSV ? 15u * (uint32_t)pbytes_m : 0u);
+    const rd_rsrc_t rMet = rd_rsrc(a.met, MET ? 4u * (uint32_t)pbytes_s : 0u);
+    const rd_rsrc_t rF_s = rd_rsrc(a.Fs, 5u * (uint32_t)pbytes_s);
+    const rd_rsrc_t rF_m = rd_rsrc(a.Fm, 5u * (uint32_t)pbytes_m);
+
+    // ---- per-tile operand fetch ---------------------------------------------------
+    // One 32-bit byte offset per K value, shared by all variables (the variable's plane
+    // is the scalar offset).  Padding K values and columns outside the tile read node 0
+    // of a valid face: their A entries are zero or their columns are never used.
+    T ls[VS][LF], lm[V][LM];
+    // column of this lane's static / moving face in tile g (a valid column also for
+    // lanes past the tile)
+    auto col_s = [&](const TileGeom &g) {
+        int i = g.i0 - 1 + col;
+        if (i < 0) i += np_;
+        return col <= g.nf ? a.fid_s[(size_t)g.row * np_ + i] : 0;
+    };
+    auto col_m = [&](const TileGeom &g) {
+        int jt = g.i0 + col - nmod - 1;
+        if (jt < 0) jt += np_;
+        return col <= g.nf ? a.fid_m[(size_t)g.row * np_ + jt] : 0;
+    };
+    auto fetch_s = [&](const TileGeom &g) {
+        const uint32_t cs = (uint32_t)col_s(g), line = (uint32_t)(NP * g.pp);
+        uint32_t os[LF];
+#pragma unroll
+        for (int ks = 0; ks < KSF; ++ks)
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int j = kidx(ks, e);
+                os[ks * E + e] = ((line + (j < NP ? j : 0)) * (uint32_t)a.nfs + cs) * (uint32_t)sizeof(T);
+            }
+#pragma unroll
+        for (int v = 0; v < VS; ++v) {
+            const rd_rsrc_t &rs = v < 5 ? rU_s : (v < V ? rG_s : rMet);
+            const int pv = v < 5 ? v : (v < V ? v - 5 : v - V);
+#pragma unroll
+            for (int q = 0; q < LF; ++q) ls[v][q] = rd_load<T>(rs, os[q], pv * pbytes_s);
+        }
+    };
+    auto fetch_m = [&](const TileGeom &g) {
+        const uint32_t cm = (uint32_t)col_m(g), line = (uint32_t)(NP * g.pp);
+        uint32_t om[LM];
+#pragma unroll
+        for (int ks = 0; ks < KSM; ++ks)
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int k = kidx(ks, e);
+                const int j = k < NP ? k : (k < 2 * NP ? k - NP : 0);
+                om[ks * E + e] = ((line + j) * (uint32_t)a.nfm + cm) * (uint32_t)sizeof(T);
+            }
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const rd_rsrc_t &rs = v < 5 ? rU_m : rG_m;
+            const int pv = v < 5 ? v : v - 5;
+#pragma unroll
+            for (int q = 0; q < LM; ++q) lm[v][q] = rd_load<T>(rs, om[q], pv * pbytes_m);
+        }
+    };
+    auto proj_s = [&](const T (&b)[LF], acc_t (&d)[RB]) {
+        op_t bo[KSF];
+#pragma unroll
+        for (int ks = 0; ks < KSF; ++ks) {
+            if constexpr (PREC == 0) bo[ks] = Op::pack(&b[ks * E]);
+            else {
+                float f[4];
+#pragma unroll
+                for (int e = 0; e < E; ++e) f[e] = (float)b[ks * E + e];
+                bo[ks] = Op::pack(f);
+            }
+        }
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            acc_t acc = {0, 0, 0, 0};
+#pragma unroll
+            for (int ks = 0; ks < KSF; ++ks) acc = Op::mma(Afs[rb][ks], bo[ks], acc);
+            d[rb] = acc;
+        }
+    };
+    auto proj_m = [&](const T (&b)[LM], acc_t (&d)[RB]) {
+        op_t bo[KSM];
+#pragma unroll
+        for (int ks = 0; ks < KSM; ++ks) {
+            T x[4];
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const T own = b[ks * E + e];
+                const T sh = rd_left(own);
+                x[e] = kidx(ks, e) < NP ? sh : own;
+            }
+            if constexpr (PREC == 0) bo[ks] = Op::pack(x);
+            else {
+                float f[4];
+#pragma unroll
+                for (int e = 0; e < E; ++e) f[e] = (float)x[e];
+                bo[ks] = Op::pack(f);
+            }
+        }
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            acc_t acc = {0, 0, 0, 0};
+#pragma unroll
+            for (int ks = 0; ks < KSM; ++ks) acc = Op::mma(Afm[rb][ks], bo[ks], acc);
+            d[rb] = acc;
+        }
+    };
+
+    WaveCursor cur(a.n_tiles, C::WAVES, wave);
+    if (!cur.valid()) return;
+    TileGeom g = tile_geom(a, cur.tile(), NP);
+    fetch_s(g);
+    fetch_m(g);
+    while (true) {
+        // The next tile's loads are issued as soon as the registers they fill are free:
+        // the static side after the static projections, the moving side after the
+        // moving ones, so that they fly while this tile's fluxes are evaluated.
+        acc_t QL[5][RB], QR[5][RB], MT[MET ? 4 : 1][RB], GL[NSV ? 15 : 1][RB], GR[NSV ? 15 : 1][RB];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) proj_s(ls[v], QL[v]);
+        if constexpr (MET) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) proj_s(ls[V + c], MT[c]);
+        }
+        if constexpr (NSV) {
+#pragma unroll
+            for (int gg = 0; gg < 15; ++gg) proj_s(ls[5 + gg], GL[gg]);
+        }
+        cur.next();
+        const bool more = cur.valid();
+        const TileGeom gc = g;
+        if (more) {
+            g = tile_geom(a, cur.tile(), NP);
+            fetch_s(g);
+        }
+#pragma unroll
+        for (int v = 0; v < 5; ++v) proj_m(lm[v], QR[v]);
+        if constexpr (NSV) {
+#pragma unroll
+            for (int gg = 0; gg < 15; ++gg) proj_m(lm[5 + gg], GR[gg]);
+        }
+        if (more) fetch_m(g);
+
+        // rows of this lane that are mortar nodes the tile needs: mortar (i0-1+col, 0)
+        // for col >= 1, mortar (i0-1+col, 1) for every live column
+        const bool live = col <= gc.nf;
+        bool use[RB][4];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int rho = rrow[rb][r];
+                use[rb][r] = live && (rho < NP ? col >= 1 : rho < 2 * NP);
+            }
+
+        // ---- flux at the lane's mortar nodes --------------------------------------------
+        // Rows that are not needed mortar nodes (padding rows, the halo column's first
+        // mortar, columns past the tile) hold values that may be anything, even
+        // non-finite; their fluxes are replaced by exact zeros below, and no other row or
+        // column ever reads them.
+        T FR[5][RB][4];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const bool u = use[rb][r];
+                T UL[5], UR[5], F[5];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) {
+                    UL[v] = T(QL[v][rb][r]);
+                    UR[v] = T(QR[v][rb][r]);
+                }
+                T nx = a.nx, ny = a.ny, nz = a.nz, dS = a.dS;
+                if constexpr (MET) {
+                    nx = MT[0][rb][r];
+                    ny = MT[1][rb][r];
+                    nz = MT[2][rb][r];
+                    dS = MT[3][rb][r];
+                }
+                convective_flux<T, RIEM>(UL, UR, nx, ny, nz, a.gas, F);
+                if constexpr (NSV) {
+                    T G[15], FvL[5], FvR[5];
+#pragma unroll
+                    for (int gg = 0; gg < 15; ++gg) G[gg] = T(GL[gg][rb][r]);
+                    viscous_flux(UL, G, nx, ny, nz, a.gas, FvL);
+#pragma unroll
+                    for (int gg = 0; gg < 15; ++gg) G[gg] = T(GR[gg][rb][r]);
+                    viscous_flux(UR, G, nx, ny, nz, a.gas, FvR);
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) F[v] -= T(0.5) * (FvL[v] + FvR[v]);
+                }
+                // rows that are not needed mortar nodes contribute nothing
+#pragma unroll
+                for (int v = 0; v < 5; ++v) FR[v][rb][r] = u ? F[v] * dS : T(0);
+            }
+
+        // ---- back projection onto both sides ----------------------------------------
+        const bool out_s = col >= 1 && col <= gc.nf;       // static face i0-1+col
+        const bool out_m = col < gc.nf;                    // moving face of slot col
+        int oc_s = 0, oc_m = 0;
+        if (out_s) oc_s = a.fid_s[(size_t)gc.row * np_ + gc.i0 - 1 + col];
+        if (out_m) {
+            int j2 = gc.i0 + col - nmod - 1;
+            if (j2 < 0) j2 += np_;
+            oc_m = a.fid_m[(size_t)gc.row * np_ + j2];
+        }
+        const uint32_t line = (uint32_t)(NP * gc.pp);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            // moving face of slot col: lower part = mortar (i0-1+col, 1) of this column,
+            // upper part = mortar (i0+col, 0) of the next column
+            T FM[RB][4];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const T nxt = rd_right(FR[v][rb][r]);
+                    FM[rb][r] = rrow[rb][r] < NP ? nxt : FR[v][rb][r];
+                }
+            acc_t ds = {0, 0, 0, 0}, dm = {0, 0, 0, 0};
+#pragma unroll
+            for (int kb = 0; kb < KSB; ++kb) {
+                T xs[4], xm[4];
+                float fs[4], fm[4];
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    int rb, r;
+                    bsrc(kb, e, rb, r);
+                    xs[e] = FR[v][rb][r];
+                    xm[e] = FM[rb][r];
+                    fs[e] = (float)xs[e];
+                    fm[e] = (float)xm[e];
+                }
+                if constexpr (PREC == 0) {
+                    ds = Op::mma(Abs[kb], Op::pack(xs), ds);
+                    dm = Op::mma(Abm[kb], Op::pack(xm), dm);
+                } else {
+                    ds = Op::mma(Abs[kb], Op::pack(fs), ds);
+                    dm = Op::mma(Abm[kb], Op::pack(fm), dm);
+                }
+            }
+            if constexpr (PREC != 0) {
+                double Ts = 0.0, Tm = 0.0, As = 0.0, Am = 0.0;
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        Ts += cw[rb][r] * (double)FR[v][rb][r];
+                        Tm += cw[rb][r] * (double)FM[rb][r];
+                    }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    As += wj[r] * (double)ds[r];
+                    Am += wj[r] * (double)dm[r];
+                }
+                // sum over the four row groups of the column (lanes col + 16 m)
+#pragma unroll
+                for (int m = 16; m <= 32; m *= 2) {
+                    Ts += __shfl_xor(Ts, m);
+                    Tm += __shfl_xor(Tm, m);
+                    As += __shfl_xor(As, m);
+                    Am += __shfl_xor(Am, m);
+                }
+                const float corr_s = (float)(0.5 * (Ts - As));   // the weights sum to 2
+                const float corr_m = (float)(0.5 * (Tm - Am));
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    ds[r] += corr_s;
+                    dm[r] += corr_m;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = Op::row(kq, r);
+                if (j < NP) {
+                    if (out_s)
+                        rd_store<T>(T(ds[r]), rF_s, ((line + j) * (uint32_t)a.nfs + oc_s) * (uint32_t)sizeof(T),
+                                    v * pbytes_s);
+                    if (out_m)
+                        rd_store<T>(T(dm[r]), rF_m, ((line + j) * (uint32_t)a.nfm + oc_m) * (uint32_t)sizeof(T),
+                                    v * pbytes_m);
+                }
+            }
+        }
+        if (!more) break;
+    }
+}
+
+}  // namespace mortar
+
+// ---- launch helpers shared by the instantiation units --------------------------------
+namespace mortar {
+
+template <typename T, int NP, bool NSV, bool MET, int RIEM, int PREC>
+static hipError_t rd_go(const FluxArgs<T> &a, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_mortar_flux_rd<T, NP, NSV, MET, RIEM, PREC>), dim3(grid), dim3(256), 0,
+                       st, a);
+    return hipGetLastError();
+}
+
+template <typename T, int NP, bool NSV, bool MET, int RIEM, int PREC>
+static int rd_occ1()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, reinterpret_cast<const void *>(&k_mortar_flux_rd<T, NP, NSV, MET, RIEM, PREC>), 256,
+            0) != hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+
+// Dispatch over (physics, metrics, Riemann solver) for one degree and precision mode.
+template <typename T, int NP, int PREC>
+static hipError_t rd_pick(const FluxArgs<T> &a, int grid, bool ns, bool met, int riem,
+                          hipStream_t st)
+{
+    if (ns) {
+        if (met) return riem ? rd_go<T, NP, true, true, 1, PREC>(a, grid, st)
+                             : rd_go<T, NP, true, true, 0, PREC>(a, grid, st);
+        return riem ? rd_go<T, NP, true, false, 1, PREC>(a, grid, st)
+                    : rd_go<T, NP, true, false, 0, PREC>(a, grid, st);
+    }
+    if (met) return riem ? rd_go<T, NP, false, true, 1, PREC>(a, grid, st)
+                         : rd_go<T, NP, false, true, 0, PREC>(a, grid, st);
+    return riem ? rd_go<T, NP, false, false, 1, PREC>(a, grid, st)
+                : rd_go<T, NP, false, false, 0, PREC>(a, grid, st);
+}
+
+template <typename T, int NP, int PREC>
+static int rd_occ(bool ns, bool met, int riem)
+{
+    if (ns) {
+        if (met) return riem ? rd_occ1<T, NP, true, true, 1, PREC>() : rd_occ1<T, NP, true, true, 0, PREC>();
+        return riem ? rd_occ1<T, NP, true, false, 1, PREC>() : rd_occ1<T, NP, true, false, 0, PREC>();
+    }
+    if (met) return riem ? rd_occ1<T, NP, false, true, 1, PREC>() : rd_occ1<T, NP, false, true, 0, PREC>();
+    return riem ? rd_occ1<T, NP, false, false, 1, PREC>() : rd_occ1<T, NP, false, false, 0, PREC>();
+}
+
+}  // namespace mortar
+
+#define MORTAR_RD_NP_SWITCH(EXPR, DEFAULT)                                              \
+    switch (NP) {                                                                       \
+    case 2: return EXPR(2); case 3: return EXPR(3); case 4: return EXPR(4);            \
+    case 5: return EXPR(5); case 6: return EXPR(6); case 7: return EXPR(7);            \
+    case 8: return EXPR(8); case 9: return EXPR(9); case 10: return EXPR(10);          \
+    default: return DEFAULT;                                                            \
+    }

@@ -31,6 +31,18 @@ hipError_t launch_flux_batch_f32(const BatchArgs<float> &b, int grid, bool ns, i
 hipError_t launch_flux_batch_f64(const BatchArgs<double> &b, int grid, bool ns, int riem,
                                  bool turbine, hipStream_t st);
 int flux_batch_occupancy_f32(bool ns, int riem, bool turbine);
+int flux_rd_occupancy_f32(int NP, bool ns, bool met, int riem);
+int flux_rd_occupancy_f64(int NP, bool ns, bool met, int riem);
+int flux_rd_occupancy_bf16(int NP, bool ns, bool met, int riem);
+int flux_rd_occupancy_fp16(int NP, bool ns, bool met, int riem);
+hipError_t launch_flux_rd_f32(const FluxArgs<float> &a, int NP, int grid, bool ns, bool met,
+                              int riem, hipStream_t st);
+hipError_t launch_flux_rd_f64(const FluxArgs<double> &a, int NP, int grid, bool ns, bool met,
+                              int riem, hipStream_t st);
+hipError_t launch_flux_rd_bf16(const FluxArgs<float> &a, int NP, int grid, bool ns, bool met,
+                               int riem, hipStream_t st);
+hipError_t launch_flux_rd_fp16(const FluxArgs<float> &a, int NP, int grid, bool ns, bool met,
+                               int riem, hipStream_t st);
 int flux_batch_occupancy_f64(bool ns, int riem, bool turbine);
 
 // ------------------------------------------------------------------------------------
@@ -185,6 +197,17 @@ static bool basis_consts(int N, int node_set, BasisConsts &c)
 
 // ------------------------------------------------------------------------------------
 
+// The register-direct kernel addresses every input and output array with 32-bit byte
+// offsets: each array must stay below 4 GiB.
+static bool rd_addressable(const mortar_iface_desc &d)
+{
+    const int64_t P = (int64_t)(d.N + 1) * (d.N + 1);
+    const int64_t elem = d.precision == MORTAR_FP64 ? 8 : 4;
+    const int64_t vars = d.physics == MORTAR_NAVIER_STOKES ? 15 : 5;
+    const int64_t nf = std::max<int64_t>(d.n_face_static, d.n_face_moving);
+    return vars * P * nf * elem < ((int64_t)1 << 32);
+}
+
 static int validate_one(const mortar_iface_desc &d)
 {
     if (d.N < 1 || d.n_par < 1 || d.n_perp < 1) return MORTAR_ERR_INVALID_ARG;
@@ -194,7 +217,7 @@ static int validate_one(const mortar_iface_desc &d)
     if (d.physics != MORTAR_EULER && d.physics != MORTAR_NAVIER_STOKES) return MORTAR_ERR_INVALID_ARG;
     if (d.riemann != MORTAR_FLUX_LF && d.riemann != MORTAR_FLUX_ROE) return MORTAR_ERR_INVALID_ARG;
     if (d.precision < MORTAR_FP64 || d.precision > MORTAR_FP16_MFMA) return MORTAR_ERR_INVALID_ARG;
-    if (d.precision == MORTAR_BF16_MFMA || d.precision == MORTAR_FP16_MFMA)
+    if ((d.precision == MORTAR_BF16_MFMA || d.precision == MORTAR_FP16_MFMA) && !rd_addressable(d))
         return MORTAR_ERR_UNSUPPORTED;
     const int64_t F = (int64_t)d.n_par * d.n_perp;
     if (F > (int64_t)1 << 28) return MORTAR_ERR_UNSUPPORTED;
@@ -325,14 +348,25 @@ static int setup_one(const mortar_iface_desc &d, Iface &f)
     {
         const bool ns = d.physics == MORTAR_NAVIER_STOKES, met = d.metrics != nullptr;
         const int riem = d.riemann == MORTAR_FLUX_ROE;
+        // kernel variant: the low-precision GEMM modes exist only in the register-direct
+        // kernel; otherwise MORTAR_FLUX_KERNEL = valu | mfma | rd selects one
         const char *kv = std::getenv("MORTAR_FLUX_KERNEL");
-        f.flux_variant = (kv && std::string(kv) == "mfma") ? 1 : 0;
+        const std::string kname = kv ? kv : "";
+        f.lp = d.precision == MORTAR_BF16_MFMA ? 1 : (d.precision == MORTAR_FP16_MFMA ? 2 : 0);
+        f.flux_variant = kname == "mfma" ? 1 : (kname == "rd" ? 2 : 0);
+        if (f.lp) f.flux_variant = 2;
+        if (f.flux_variant == 2 && !rd_addressable(d)) f.flux_variant = 0;
         if (f.flux_variant == 0)
             f.flux_occ = f.elem == 8 ? flux_occupancy_f64(f.NP, ns, met, riem)
                                      : flux_occupancy_f32(f.NP, ns, met, riem);
-        else
+        else if (f.flux_variant == 1)
             f.flux_occ = f.elem == 8 ? flux_mfma_occupancy_f64(f.NP, ns, met, riem)
                                      : flux_mfma_occupancy_f32(f.NP, ns, met, riem);
+        else
+            f.flux_occ = f.lp == 1 ? flux_rd_occupancy_bf16(f.NP, ns, met, riem)
+                       : f.lp == 2 ? flux_rd_occupancy_fp16(f.NP, ns, met, riem)
+                              : (f.elem == 8 ? flux_rd_occupancy_f64(f.NP, ns, met, riem)
+                                             : flux_rd_occupancy_f32(f.NP, ns, met, riem));
     }
     f.n_cons_blocks = std::min(256, std::max(1, (f.F + 255) / 256));
     if (hipMalloc((void **)&f.d_cons, sizeof(double) * 30 * (size_t)f.n_cons_blocks) != hipSuccess)
@@ -750,7 +784,7 @@ void fill_args(const Iface &f, const void *Us, const void *Um, const void *Gs,
     const double gm1 = f.d.gamma - 1.0;
     const double kfac = ns ? f.d.mu * f.d.gamma / (gm1 * f.d.Pr) : 0.0;
     const int64_t np = f.d.n_par;
-    const int cap = f.flux_variant == 1 ? 15
+    const int cap = f.flux_variant != 0 ? 15
                   : (f.elem == 8 ? flux_tile_capacity_f64(f.NP, ns, met)
                                  : flux_tile_capacity_f32(f.NP, ns, met));
     // balanced tiles: as few as the capacity allows, all of nearly equal length
@@ -782,6 +816,22 @@ hipError_t launch_flux(const Iface &f, int n_cu, const void *Us, const void *Um,
     const bool met = f.d_metrics != nullptr;
     const int riem = f.d.riemann == MORTAR_FLUX_ROE ? 1 : 0;
     int n_tiles = 0;
+    if (f.flux_variant == 2) {
+        // one tile per wave, four waves per workgroup; at least one workgroup per XCD
+        auto rd_grid = [&](int nt) {
+            return std::max(8, std::min((nt + 3) / 4, f.flux_occ * n_cu));
+        };
+        if (f.elem == 8) {
+            FluxArgs<double> a;
+            fill_args(f, Us, Um, Gs, Gm, Fs, Fm, a, n_tiles);
+            return launch_flux_rd_f64(a, f.NP, rd_grid(n_tiles), ns, met, riem, st);
+        }
+        FluxArgs<float> a;
+        fill_args(f, Us, Um, Gs, Gm, Fs, Fm, a, n_tiles);
+        if (f.lp == 1) return launch_flux_rd_bf16(a, f.NP, rd_grid(n_tiles), ns, met, riem, st);
+        if (f.lp == 2) return launch_flux_rd_fp16(a, f.NP, rd_grid(n_tiles), ns, met, riem, st);
+        return launch_flux_rd_f32(a, f.NP, rd_grid(n_tiles), ns, met, riem, st);
+    }
     if (f.elem == 8) {
         FluxArgs<double> a;
         fill_args(f, Us, Um, Gs, Gm, Fs, Fm, a, n_tiles);

@@ -70,7 +70,9 @@ struct Iface {
     double *d_cons = nullptr;          // conservation partials
     int n_cons_blocks = 0;
     int flux_occ = 1;                  // resident flux workgroups per CU
-    int flux_variant = 1;              // 0: VALU projections, 1: matrix-core projections
+    int flux_variant = 0;              // 0: VALU projections, 1: matrix-core projections
+                                       // staged in LDS, 2: register-direct matrix-core kernel
+    int lp = 0;                        // GEMM operands: 0 element type, 1 bf16, 2 fp16
 };
 
 struct Handle {
