@@ -35,6 +35,8 @@ def parse():
     p.add_argument("--cpu-stages", type=int, default=10)
     p.add_argument("--rotate-bytes", type=float, default=1.2e9)
     p.add_argument("--graph", action="store_true", help="replay a captured HIP graph per stage")
+    p.add_argument("--no-autotune", action="store_true",
+                   help="launch with the library defaults instead of autotuned launches")
     p.add_argument("--precision", choices=("fp32", "bf16", "fp16"), default="fp32",
                    help="headline leg: FP32, or FP32 data with bf16 / fp16 projection GEMMs")
     p.add_argument("--copy-calibration", type=float, default=0.0,
@@ -67,10 +69,11 @@ def algorithmic_bytes(spec):
     return total
 
 
-def run_leg(M, W, specs, disp, steps, warmup, rotate_bytes, graph=False, plain=False):
+def run_leg(M, W, specs, disp, steps, warmup, rotate_bytes, graph=False, plain=False, tune=True):
     """Times one precision of a workload.  plain: one handle (one launch) per interface
     instead of the batched persistent launch; graph: each stage replays a captured HIP
-    graph instead of eager launches."""
+    graph instead of eager launches; tune: the library's autotuner picks each launch
+    (kernel variant, tile length, grid) first, outside the timed region."""
     import numpy as np
     import torch
 
@@ -104,6 +107,17 @@ def run_leg(M, W, specs, disp, steps, warmup, rotate_bytes, graph=False, plain=F
         sel = range(len(specs)) if sel is None else sel
         return ([per[i]["Us"] for i in sel], [per[i]["Um"] for i in sel], [per[i]["Gs"] for i in sel],
                 [per[i]["Gm"] for i in sel], [per[i]["Fs"] for i in sel], [per[i]["Fm"] for i in sel])
+
+    tuning = None
+    if tune:
+        t1 = time.time()
+        tuning = []
+        for i, op in enumerate(ops):
+            sel = [i] if plain else None
+            op.update([disp(0)[i]] if plain else disp(0))
+            tuning += op.autotune(*args(sets[0], sel), reps=3)
+        torch.cuda.synchronize()
+        print(f"[bench] autotune {time.time() - t1:.2f} s: {tuning}", file=sys.stderr, flush=True)
 
     graphs = None
     if graph:
@@ -179,6 +193,7 @@ def run_leg(M, W, specs, disp, steps, warmup, rotate_bytes, graph=False, plain=F
         "frac": achieved / HBM_PEAK_GBS,
         "conservation_rel_residual": cons_rel,
         "rotated_sets": nsets,
+        "tuning": tuning,
     }
 
 
@@ -223,12 +238,14 @@ def main():
     torch.cuda.set_device(0)
     prec = {"fp32": W.FP32, "bf16": W.BF16_MFMA, "fp16": W.FP16_MFMA}[a.precision]
     specs32, disp = W.config(a.config, precision=prec)
-    r32 = run_leg(M, W, specs32, disp, a.steps, a.warmup, a.rotate_bytes, graph=a.graph)
+    r32 = run_leg(M, W, specs32, disp, a.steps, a.warmup, a.rotate_bytes, graph=a.graph,
+                  tune=not a.no_autotune)
     r64 = None
     if not a.no_fp64:
         specs64, _ = W.config(a.config, precision=W.FP64)
         # the comparison point: plain FP64, one launch per interface
-        r64 = run_leg(M, W, specs64, disp, a.steps, a.warmup, a.rotate_bytes, plain=True)
+        r64 = run_leg(M, W, specs64, disp, a.steps, a.warmup, a.rotate_bytes, plain=True,
+                      tune=not a.no_autotune)
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(W, specs64 if r64 else specs32, disp, a.cpu_stages)
@@ -265,12 +282,13 @@ def main():
                        "value": r64["pts_per_s"], "ms_per_step": r64["ms_per_step"],
                        "kernel_ms_avg": r64["kernel_ms_avg"], "achieved_GBs": r64["achieved_GBs"],
                        "frac": r64["frac"],
-                       "conservation_rel_residual": r64["conservation_rel_residual"]},
+                       "conservation_rel_residual": r64["conservation_rel_residual"],
+                       "tuning": r64["tuning"]},
                    "fp32_kernel": {k: r32[k] for k in ("kernel_ms_avg", "kernel_ms_median",
                                                        "kernel_ms_min", "kernel_ms_max",
                                                        "kernel_pts_per_s",
                                                        "conservation_rel_residual",
-                                                       "rotated_sets")}},
+                                                       "rotated_sets", "tuning")}},
         "roofline": {"bound": "hbm", "achieved": r32["achieved_GBs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": r32["frac"], "traffic": None,
                      "kernel": kname.get(a.config),

@@ -138,6 +138,39 @@ int mortar_graph_create(mortar_handle *h, const void *const *U_s, const void *co
 int mortar_graph_launch(mortar_graph *g, const double *disp, void *stream);
 int mortar_graph_destroy(mortar_graph *g);
 
+/* ---- launch tuning ----------------------------------------------------------------
+ * How an interface's flux is launched.  variant: MORTAR_KERNEL_VALU (projections on the
+ * vector units, tiles staged in LDS), MORTAR_KERNEL_MFMA_LDS (projections as matrix-core
+ * GEMMs, tiles staged in LDS), MORTAR_KERNEL_REGISTER (one wave per tile, GEMM results
+ * kept in registers; the only variant of the bf16/fp16 precisions).  tile_len: output
+ * faces per tile along the sliding direction (0 = the variant's largest; larger values
+ * are capped to it).  grid: workgroups of the persistent launch (0 = every resident
+ * slot of the device; otherwise at least 8, one per XCD).  Interfaces in one batched
+ * launch share the VALU variant and the grid; each has its own tile_len. */
+enum { MORTAR_KERNEL_VALU = 0, MORTAR_KERNEL_MFMA_LDS = 1, MORTAR_KERNEL_REGISTER = 2 };
+typedef struct mortar_tuning {
+    int32_t variant;
+    int32_t tile_len;
+    int32_t grid;
+    int32_t reserved;       /* 0 */
+} mortar_tuning;
+
+/* Autotuner: times the candidate launches of every interface on the given buffers
+ * (conventions of mortar_flux; F_s/F_m are overwritten) with HIP events on stream, reps
+ * launches per candidate after one warm-up, and keeps the fastest.  Candidates: each
+ * applicable variant with three tile lengths (single-interface launches), or three tile
+ * lengths per interface and the grid (batched launch).  Needs a displacement already
+ * set; synchronizes stream; allocates nothing on the device.  Graphs captured before a
+ * tuning change are refused by mortar_graph_launch (UNSUPPORTED): capture them again. */
+int mortar_autotune(mortar_handle *h, const void *const *U_s, const void *const *U_m,
+                    const void *const *G_s, const void *const *G_m, void *const *F_s,
+                    void *const *F_m, int reps, void *stream);
+
+/* Current tuning of interface iface (host struct), and setting one (e.g. from a cache of
+ * an earlier mortar_autotune).  INVALID_ARG for a variant the interface cannot use. */
+int mortar_get_tuning(const mortar_handle *h, int iface, mortar_tuning *out);
+int mortar_set_tuning(mortar_handle *h, int iface, const mortar_tuning *t);
+
 /* Frees the handle and its device buffers (synchronizes the device first). */
 int mortar_destroy(mortar_handle *h);
 

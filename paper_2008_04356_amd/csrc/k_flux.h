@@ -415,18 +415,45 @@ constexpr size_t batch_smem()
 // same share of its tiles (see TileCursor) and each workgroup assembles that interface's
 // matrices once.  MASK: bit NP set for every degree this instantiation serves; the host
 // only launches it for batches whose degrees are all in MASK.
+// One interface of a batch as a real call: each degree's code keeps its own register
+// allocation, so the batched kernel needs only as many registers as its largest
+// degree (inlining every degree into one body costs more than any of them alone).
+template <typename T, int NP, bool NSV, bool MET, int RIEM, int BUDGET>
+__device__ __noinline__ void run_interface_call(const FluxArgs<T> *a, char *smem)
+{
+    TileCursor cur(a->n_tiles);
+    run_interface<T, NP, NSV, MET, RIEM, BUDGET>(*a, cur, smem);
+}
+
+template <typename T, int NP, bool NSV, bool MET, int RIEM, int BUDGET, bool CALL>
+__device__ __forceinline__ void run_batch_member(const FluxArgs<T> *a, char *smem)
+{
+    if constexpr (CALL) {
+        run_interface_call<T, NP, NSV, MET, RIEM, BUDGET>(a, smem);
+    } else {
+        TileCursor cur(a->n_tiles);
+        run_interface<T, NP, NSV, MET, RIEM, BUDGET>(*a, cur, smem);
+    }
+}
+
+// The three-degree turbine set is inlined with the register budget of two waves per
+// SIMD; the every-degree instantiation calls one function per degree.
+template <int MASK>
+constexpr bool batch_calls() { return MASK != kMaskTurbine; }
+
 template <typename T, bool NSV, int RIEM, int BUDGET, int MASK>
-__global__ __launch_bounds__(kFluxThreads) void k_mortar_flux_batch(BatchArgs<T> b)
+__global__ __launch_bounds__(kFluxThreads) __attribute__((amdgpu_waves_per_eu(2)))
+void k_mortar_flux_batch(BatchArgs<T> b)
 {
     __shared__ __attribute__((aligned(16))) char smem[batch_smem<T, NSV, BUDGET, MASK>()];
+    constexpr bool CALL = batch_calls<MASK>();
     for (int i = 0; i < b.n_if; ++i) {
-        TileCursor cur(b.a[i].n_tiles);
-        if (!cur.valid()) continue;          // uniform over the workgroup
+        if (!TileCursor(b.a[i].n_tiles).valid()) continue;   // uniform over the workgroup
         const bool met = b.met[i] != 0;
 #define MORTAR_BATCH_NP(NPV)                                                             \
     if ((MASK & (1 << NPV)) && b.np[i] == NPV) {                                         \
-        if (met) run_interface<T, NPV, NSV, true, RIEM, BUDGET>(b.a[i], cur, smem);      \
-        else run_interface<T, NPV, NSV, false, RIEM, BUDGET>(b.a[i], cur, smem);         \
+        if (met) run_batch_member<T, NPV, NSV, true, RIEM, BUDGET, CALL>(&b.a[i], smem); \
+        else run_batch_member<T, NPV, NSV, false, RIEM, BUDGET, CALL>(&b.a[i], smem);    \
         continue;                                                                        \
     }
         MORTAR_BATCH_NP(2) MORTAR_BATCH_NP(3) MORTAR_BATCH_NP(4) MORTAR_BATCH_NP(5)

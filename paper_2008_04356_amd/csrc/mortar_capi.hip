@@ -295,6 +295,28 @@ static void owner_ids(const int32_t *own, int64_t F, std::vector<int32_t> &ids,
         ids[i] = (int32_t)(std::lower_bound(vals.begin(), vals.end(), own[i]) - vals.begin());
 }
 
+// Resident workgroups per CU of a kernel variant for this interface.
+static int variant_occupancy(const Iface &f, int variant)
+{
+    const bool ns = f.d.physics == MORTAR_NAVIER_STOKES, met = f.d_metrics != nullptr;
+    const int riem = f.d.riemann == MORTAR_FLUX_ROE;
+    if (variant == 0)
+        return f.elem == 8 ? flux_occupancy_f64(f.NP, ns, met, riem) : flux_occupancy_f32(f.NP, ns, met, riem);
+    if (variant == 1)
+        return f.elem == 8 ? flux_mfma_occupancy_f64(f.NP, ns, met, riem)
+                           : flux_mfma_occupancy_f32(f.NP, ns, met, riem);
+    if (f.lp == 1) return flux_rd_occupancy_bf16(f.NP, ns, met, riem);
+    if (f.lp == 2) return flux_rd_occupancy_fp16(f.NP, ns, met, riem);
+    return f.elem == 8 ? flux_rd_occupancy_f64(f.NP, ns, met, riem) : flux_rd_occupancy_f32(f.NP, ns, met, riem);
+}
+
+static bool variant_allowed(const Iface &f, int variant)
+{
+    if (variant < 0 || variant > 2) return false;
+    if (f.lp) return variant == 2;
+    return variant != 2 || rd_addressable(f.d);
+}
+
 static int setup_one(const mortar_iface_desc &d, Iface &f)
 {
     f.d = d;
@@ -355,18 +377,9 @@ static int setup_one(const mortar_iface_desc &d, Iface &f)
         f.lp = d.precision == MORTAR_BF16_MFMA ? 1 : (d.precision == MORTAR_FP16_MFMA ? 2 : 0);
         f.flux_variant = kname == "mfma" ? 1 : (kname == "rd" ? 2 : 0);
         if (f.lp) f.flux_variant = 2;
-        if (f.flux_variant == 2 && !rd_addressable(d)) f.flux_variant = 0;
-        if (f.flux_variant == 0)
-            f.flux_occ = f.elem == 8 ? flux_occupancy_f64(f.NP, ns, met, riem)
-                                     : flux_occupancy_f32(f.NP, ns, met, riem);
-        else if (f.flux_variant == 1)
-            f.flux_occ = f.elem == 8 ? flux_mfma_occupancy_f64(f.NP, ns, met, riem)
-                                     : flux_mfma_occupancy_f32(f.NP, ns, met, riem);
-        else
-            f.flux_occ = f.lp == 1 ? flux_rd_occupancy_bf16(f.NP, ns, met, riem)
-                       : f.lp == 2 ? flux_rd_occupancy_fp16(f.NP, ns, met, riem)
-                              : (f.elem == 8 ? flux_rd_occupancy_f64(f.NP, ns, met, riem)
-                                             : flux_rd_occupancy_f32(f.NP, ns, met, riem));
+        if (!variant_allowed(f, f.flux_variant)) f.flux_variant = 0;
+        f.flux_occ = variant_occupancy(f, f.flux_variant);
+        (void)ns; (void)met; (void)riem;
     }
     f.n_cons_blocks = std::min(256, std::max(1, (f.F + 255) / 256));
     if (hipMalloc((void **)&f.d_cons, sizeof(double) * 30 * (size_t)f.n_cons_blocks) != hipSuccess)
@@ -423,6 +436,7 @@ struct mortar_handle : public mortar::Handle {};
 // A captured stage: the flux launch(es) of a handle for fixed buffers.
 struct mortar_graph {
     mortar_handle *h = nullptr;
+    unsigned epoch = 0;                      // tuning epoch of the handle at capture
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<hipGraphNode_t> nodes;       // kernel nodes in launch order
@@ -650,6 +664,7 @@ int mortar_graph_create(mortar_handle *h, const void *const *U_s, const void *co
     mortar_graph *g = new (std::nothrow) mortar_graph();
     if (!g) return MORTAR_ERR_OOM;
     g->h = h;
+    g->epoch = h->tune_epoch;
     for (size_t i = 0; i < n_if; ++i) {
         g->Us.push_back(U_s[i]);
         g->Um.push_back(U_m[i]);
@@ -718,6 +733,7 @@ int mortar_graph_launch(mortar_graph *g, const double *disp, void *stream)
 {
     if (!g || !g->exec || !disp) return MORTAR_ERR_INVALID_ARG;
     mortar_handle *h = g->h;
+    if (g->epoch != h->tune_epoch) return MORTAR_ERR_UNSUPPORTED;   // captured before a retune
     int rc = mortar_update_displacement(h, disp, stream);
     if (rc) return rc;
     const size_t n_if = h->ifs.size();
@@ -761,6 +777,142 @@ int mortar_graph_launch(mortar_graph *g, const double *disp, void *stream)
     return MORTAR_OK;
 }
 
+// ---- autotuner ------------------------------------------------------------------------
+
+}  // extern "C"
+
+// Average time of one launch (ms): one warm-up, then reps launches between two events.
+template <typename F>
+static hipError_t time_launches(F &&launch, int reps, hipStream_t st, float &ms)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t err = hipEventCreate(&e0);
+    if (err == hipSuccess) err = hipEventCreate(&e1);
+    if (err == hipSuccess) err = launch();
+    if (err == hipSuccess) err = hipEventRecord(e0, st);
+    for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch();
+    if (err == hipSuccess) err = hipEventRecord(e1, st);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    if (err == hipSuccess) ms /= (float)reps;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return err;
+}
+
+// Three tile lengths per capacity: the largest, about two thirds and about half.
+static std::vector<int> tile_candidates(int cap)
+{
+    std::vector<int> t = {cap, std::max(2, (2 * cap + 2) / 3), std::max(2, (cap + 1) / 2)};
+    std::sort(t.begin(), t.end());
+    t.erase(std::unique(t.begin(), t.end()), t.end());
+    return t;
+}
+
+static int vmax_tile(const Iface &f, int variant)
+{
+    const bool ns = f.d.physics == MORTAR_NAVIER_STOKES, met = f.d_metrics != nullptr;
+    if (variant != 0) return 15;
+    return f.elem == 8 ? flux_tile_capacity_f64(f.NP, ns, met) : flux_tile_capacity_f32(f.NP, ns, met);
+}
+
+extern "C" {
+
+int mortar_autotune(mortar_handle *h, const void *const *U_s, const void *const *U_m,
+                    const void *const *G_s, const void *const *G_m, void *const *F_s,
+                    void *const *F_m, int reps, void *stream)
+{
+    if (!h || !U_s || !U_m || !F_s || !F_m) return MORTAR_ERR_INVALID_ARG;
+    if (reps <= 0) reps = 5;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t n_if = h->ifs.size();
+    for (size_t i = 0; i < n_if; ++i) {
+        const Iface &f = h->ifs[i];
+        if (!f.ready) return MORTAR_ERR_NOT_READY;
+        const bool ns = f.d.physics == MORTAR_NAVIER_STOKES;
+        if (!U_s[i] || !U_m[i] || !F_s[i] || !F_m[i]) return MORTAR_ERR_INVALID_ARG;
+        if (ns && (!G_s || !G_m || !G_s[i] || !G_m[i])) return MORTAR_ERR_INVALID_ARG;
+    }
+    h->tune_epoch++;
+    float ms = 0.f;
+    if (h->batched) {
+        auto run = [&]() { return launch_flux_batched(*h, U_s, U_m, G_s, G_m, F_s, F_m, st); };
+        // coordinate descent: each interface's tile length, then the grid
+        for (size_t i = 0; i < n_if; ++i) {
+            Iface &f = h->ifs[i];
+            int best_t = f.tune_tile;
+            float best = 1e30f;
+            for (int t : tile_candidates(vmax_tile(f, 0))) {
+                f.tune_tile = t;
+                TRY_HIP(time_launches(run, reps, st, ms));
+                if (ms < best) { best = ms; best_t = t; }
+            }
+            f.tune_tile = best_t;
+        }
+        int best_g = 0;
+        float best = 1e30f;
+        for (int k = h->batch_occ; k >= 1; --k) {
+            h->tune_grid_batch = k == h->batch_occ ? 0 : k * h->n_cu;
+            TRY_HIP(time_launches(run, reps, st, ms));
+            if (ms < best) { best = ms; best_g = h->tune_grid_batch; }
+        }
+        h->tune_grid_batch = best_g;
+        return MORTAR_OK;
+    }
+    for (size_t i = 0; i < n_if; ++i) {
+        Iface &f = h->ifs[i];
+        const bool ns = f.d.physics == MORTAR_NAVIER_STOKES;
+        auto run = [&]() {
+            return launch_flux(f, h->n_cu, U_s[i], U_m[i], ns ? G_s[i] : nullptr,
+                               ns ? G_m[i] : nullptr, F_s[i], F_m[i], st);
+        };
+        int best_v = f.flux_variant, best_t = f.tune_tile;
+        float best = 1e30f;
+        for (int v = 0; v <= 2; ++v) {
+            if (!variant_allowed(f, v)) continue;
+            f.flux_variant = v;
+            f.flux_occ = variant_occupancy(f, v);
+            f.tune_grid = 0;
+            for (int t : tile_candidates(vmax_tile(f, v))) {
+                f.tune_tile = t;
+                TRY_HIP(time_launches(run, reps, st, ms));
+                if (ms < best) { best = ms; best_v = v; best_t = t; }
+            }
+        }
+        f.flux_variant = best_v;
+        f.flux_occ = variant_occupancy(f, best_v);
+        f.tune_tile = best_t;
+    }
+    return MORTAR_OK;
+}
+
+int mortar_get_tuning(const mortar_handle *h, int iface, mortar_tuning *out)
+{
+    if (!h || !out || iface < 0 || iface >= (int)h->ifs.size()) return MORTAR_ERR_INVALID_ARG;
+    const Iface &f = h->ifs[iface];
+    out->variant = f.flux_variant;
+    out->tile_len = f.tune_tile;
+    out->grid = h->batched ? h->tune_grid_batch : f.tune_grid;
+    out->reserved = 0;
+    return MORTAR_OK;
+}
+
+int mortar_set_tuning(mortar_handle *h, int iface, const mortar_tuning *t)
+{
+    if (!h || !t || iface < 0 || iface >= (int)h->ifs.size()) return MORTAR_ERR_INVALID_ARG;
+    if (t->tile_len < 0 || t->grid < 0 || (t->grid > 0 && t->grid < 8)) return MORTAR_ERR_INVALID_ARG;
+    Iface &f = h->ifs[iface];
+    if (!variant_allowed(f, t->variant)) return MORTAR_ERR_INVALID_ARG;
+    if (h->batched && t->variant != 0) return MORTAR_ERR_INVALID_ARG;
+    h->tune_epoch++;
+    f.flux_variant = t->variant;
+    f.flux_occ = variant_occupancy(f, t->variant);
+    f.tune_tile = t->tile_len;
+    if (h->batched) h->tune_grid_batch = t->grid;
+    else f.tune_grid = t->grid;
+    return MORTAR_OK;
+}
+
 int mortar_graph_destroy(mortar_graph *g)
 {
     if (!g) return MORTAR_ERR_INVALID_ARG;
@@ -784,9 +936,10 @@ void fill_args(const Iface &f, const void *Us, const void *Um, const void *Gs,
     const double gm1 = f.d.gamma - 1.0;
     const double kfac = ns ? f.d.mu * f.d.gamma / (gm1 * f.d.Pr) : 0.0;
     const int64_t np = f.d.n_par;
-    const int cap = f.flux_variant != 0 ? 15
-                  : (f.elem == 8 ? flux_tile_capacity_f64(f.NP, ns, met)
-                                 : flux_tile_capacity_f32(f.NP, ns, met));
+    int cap = f.flux_variant != 0 ? 15
+            : (f.elem == 8 ? flux_tile_capacity_f64(f.NP, ns, met)
+                           : flux_tile_capacity_f32(f.NP, ns, met));
+    if (f.tune_tile > 0) cap = std::min(cap, f.tune_tile);
     // balanced tiles: as few as the capacity allows, all of nearly equal length
     const int tiles_per_row = (f.d.n_par + cap - 1) / cap;
     const int tile_len = (f.d.n_par + tiles_per_row - 1) / tiles_per_row;
@@ -819,6 +972,7 @@ hipError_t launch_flux(const Iface &f, int n_cu, const void *Us, const void *Um,
     if (f.flux_variant == 2) {
         // one tile per wave, four waves per workgroup; at least one workgroup per XCD
         auto rd_grid = [&](int nt) {
+            if (f.tune_grid > 0) return std::max(8, f.tune_grid);
             return std::max(8, std::min((nt + 3) / 4, f.flux_occ * n_cu));
         };
         if (f.elem == 8) {
@@ -832,16 +986,22 @@ hipError_t launch_flux(const Iface &f, int n_cu, const void *Us, const void *Um,
         if (f.lp == 2) return launch_flux_rd_fp16(a, f.NP, rd_grid(n_tiles), ns, met, riem, st);
         return launch_flux_rd_f32(a, f.NP, rd_grid(n_tiles), ns, met, riem, st);
     }
+    // persistent grid: at least min(8, n_tiles) workgroups so that every XCD's share of
+    // the tiles has workers (TileCursor)
+    auto grid_of = [&](int nt) {
+        if (f.tune_grid > 0) return std::max(std::min(8, nt), std::min(nt, f.tune_grid));
+        return std::max(1, std::min(nt, f.flux_occ * n_cu));
+    };
     if (f.elem == 8) {
         FluxArgs<double> a;
         fill_args(f, Us, Um, Gs, Gm, Fs, Fm, a, n_tiles);
-        const int grid = std::max(1, std::min(n_tiles, f.flux_occ * n_cu));
+        const int grid = grid_of(n_tiles);
         return f.flux_variant == 1 ? launch_flux_mfma_f64(a, f.NP, grid, ns, met, riem, st)
                                    : launch_flux_f64(a, f.NP, grid, ns, met, riem, st);
     }
     FluxArgs<float> a;
     fill_args(f, Us, Um, Gs, Gm, Fs, Fm, a, n_tiles);
-    const int grid = std::max(1, std::min(n_tiles, f.flux_occ * n_cu));
+    const int grid = grid_of(n_tiles);
     return f.flux_variant == 1 ? launch_flux_mfma_f32(a, f.NP, grid, ns, met, riem, st)
                                : launch_flux_f32(a, f.NP, grid, ns, met, riem, st);
 }
@@ -866,15 +1026,19 @@ hipError_t launch_flux_batched(const Handle &h, const void *const *Us, const voi
             total += nt;
         }
     };
+    auto grid_of = [&](int nt) {
+        if (h.tune_grid_batch > 0) return std::max(std::min(8, nt), std::min(nt, h.tune_grid_batch));
+        return std::max(1, std::min(nt, h.batch_occ * h.n_cu));
+    };
     if (f0.elem == 8) {
         BatchArgs<double> b;
         build(b);
-        const int grid = std::max(1, std::min(total, h.batch_occ * h.n_cu));
+        const int grid = grid_of(total);
         return launch_flux_batch_f64(b, grid, ns, riem, h.batch_turbine, st);
     }
     BatchArgs<float> b;
     build(b);
-    const int grid = std::max(1, std::min(total, h.batch_occ * h.n_cu));
+    const int grid = grid_of(total);
     return launch_flux_batch_f32(b, grid, ns, riem, h.batch_turbine, st);
 }
 

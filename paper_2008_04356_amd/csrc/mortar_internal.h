@@ -73,6 +73,8 @@ struct Iface {
     int flux_variant = 0;              // 0: VALU projections, 1: matrix-core projections
                                        // staged in LDS, 2: register-direct matrix-core kernel
     int lp = 0;                        // GEMM operands: 0 element type, 1 bf16, 2 fp16
+    int tune_tile = 0;                 // tile length cap from tuning (0: variant's largest)
+    int tune_grid = 0;                 // workgroups from tuning (0: all resident slots)
 };
 
 struct Handle {
@@ -81,6 +83,8 @@ struct Handle {
     bool batched = false;              // all interfaces go in one persistent launch
     bool batch_turbine = false;        // the N = 3, 5, 7 instantiation covers the batch
     int batch_occ = 1;
+    int tune_grid_batch = 0;           // workgroups of the batched launch (0: default)
+    unsigned tune_epoch = 0;           // bumped by every tuning change
     std::vector<Iface> ifs;
 };
 

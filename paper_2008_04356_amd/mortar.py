@@ -42,6 +42,14 @@ class mortar_iface_desc(C.Structure):
     ]
 
 
+class mortar_tuning(C.Structure):
+    _fields_ = [("variant", C.c_int32), ("tile_len", C.c_int32), ("grid", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+KERNEL_VALU, KERNEL_MFMA_LDS, KERNEL_REGISTER = 0, 1, 2
+
+
 class MortarError(RuntimeError):
     pass
 
@@ -69,6 +77,10 @@ def _load():
                                       C.POINTER(C.c_void_p)]
     L.mortar_graph_launch.argtypes = [C.c_void_p, _dp, C.c_void_p]
     L.mortar_graph_destroy.argtypes = [C.c_void_p]
+    L.mortar_autotune.argtypes = [C.c_void_p, _vpp, _vpp, _vpp, _vpp, _vpp, _vpp, C.c_int,
+                                  C.c_void_p]
+    L.mortar_get_tuning.argtypes = [C.c_void_p, C.c_int, C.POINTER(mortar_tuning)]
+    L.mortar_set_tuning.argtypes = [C.c_void_p, C.c_int, C.POINTER(mortar_tuning)]
     return L
 
 
@@ -131,6 +143,22 @@ def mortar_graph_launch(g, disp: Sequence[float], stream: int = 0) -> int:
 
 def mortar_graph_destroy(g) -> int:
     return lib.mortar_graph_destroy(g)
+
+
+def mortar_autotune(h, Us, Um, Gs, Gm, Fs, Fm, reps: int = 5, stream: int = 0) -> int:
+    return lib.mortar_autotune(h, _ptrs(Us), _ptrs(Um), _ptrs(Gs), _ptrs(Gm), _ptrs(Fs),
+                               _ptrs(Fm), int(reps), C.c_void_p(stream))
+
+
+def mortar_get_tuning(h, iface: int):
+    t = mortar_tuning()
+    _check(lib.mortar_get_tuning(h, iface, C.byref(t)), "mortar_get_tuning")
+    return {"variant": t.variant, "tile_len": t.tile_len, "grid": t.grid}
+
+
+def mortar_set_tuning(h, iface: int, variant: int, tile_len: int = 0, grid: int = 0) -> int:
+    t = mortar_tuning(int(variant), int(tile_len), int(grid), 0)
+    return lib.mortar_set_tuning(h, iface, C.byref(t))
 
 
 def mortar_destroy(h) -> int:
@@ -238,6 +266,50 @@ class MortarOperator:
         p = lambda ts: None if ts is None else [None if t is None else t.data_ptr() for t in ts]  # noqa: E731
         _check(mortar_flux(self.h, p(Us), p(Um), p(Gs), p(Gm), p(Fs), p(Fm), self._stream(stream)),
                "mortar_flux")
+
+    def tuning_key(self):
+        """What a tuning depends on: the device, and every interface's shape and mode."""
+        import torch
+        dev = torch.cuda.get_device_properties(torch.cuda.current_device())
+        arch = getattr(dev, "gcnArchName", dev.name)
+        parts = [f"{s.N}/{s.node_set}/{s.n_par}x{s.n_perp}/{s.n_face_static},{s.n_face_moving}/"
+                 f"{s.physics}/{s.riemann}/{s.precision}/{int(s.metrics is not None)}"
+                 for s in self.specs]
+        return arch + "|" + ";".join(parts)
+
+    def tuning(self):
+        return [mortar_get_tuning(self.h, i) for i in range(len(self.specs))]
+
+    def set_tuning(self, tunings):
+        for i, t in enumerate(tunings):
+            _check(mortar_set_tuning(self.h, i, t["variant"], t["tile_len"], t["grid"]),
+                   "mortar_set_tuning")
+
+    def autotune(self, Us, Um, Gs, Gm, Fs, Fm, reps=5, cache=None, stream=None):
+        """Picks the launch of every interface by timing the candidates on these buffers
+        (outputs are overwritten).  cache: path of a JSON file mapping tuning_key() to the
+        chosen tunings; a hit applies the stored choice without timing."""
+        import json
+        import os
+        key = self.tuning_key()
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as fh:
+                table = json.load(fh)
+            if key in table:
+                self.set_tuning(table[key])
+                return table[key]
+        p = lambda ts: None if ts is None else [None if t is None else t.data_ptr() for t in ts]  # noqa: E731
+        _check(mortar_autotune(self.h, p(Us), p(Um), p(Gs), p(Gm), p(Fs), p(Fm), reps,
+                               self._stream(stream)), "mortar_autotune")
+        chosen = self.tuning()
+        if cache:
+            table[key] = chosen
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as fh:
+                json.dump(table, fh, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return chosen
 
     def displacement(self, iface=0):
         n = C.c_int64()
