@@ -5,7 +5,8 @@ Workload (default): plane sliding interface, N = 5 (6x6 Gauss points per face),
 point), Roe + Harten-Hyman + BR1 viscous flux, mu = 1e-4, displacement 0.0137 l_par per
 stage (constant sliding speed; crosses whole faces every ~73 stages).  One step = one
 Runge-Kutta stage of the operator: displacement update (split, index map on crossings,
-FP64 projection-matrix assembly) + the fused mortar flux.  Inputs are resident in HBM;
+FP64 projection-matrix assembly) + the fused mortar flux + the FP64 conservation residual
+sums of the stage's fluxes (on the device, no synchronization).  Inputs are resident in HBM;
 input/output sets are rotated (> 1 GB) so the 256 MB Infinity Cache cannot hold them.
 
 Prints one JSON line: headline value = FP32 mortar points/s; the plain FP64 run of the
@@ -32,11 +33,13 @@ def parse():
     p.add_argument("--config", type=int, default=2)
     p.add_argument("--no-fp64", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-stages", type=int, default=10)
+    p.add_argument("--cpu-stages", type=int, default=30)
     p.add_argument("--rotate-bytes", type=float, default=1.2e9)
     p.add_argument("--graph", action="store_true", help="replay a captured HIP graph per stage")
     p.add_argument("--no-autotune", action="store_true",
                    help="launch with the library defaults instead of autotuned launches")
+    p.add_argument("--tune-cache", default=None,
+                   help="JSON file of earlier autotuner choices (read, and written on a miss)")
     p.add_argument("--precision", choices=("fp32", "bf16", "fp16"), default="fp32",
                    help="headline leg: FP32, or FP32 data with bf16 / fp16 projection GEMMs")
     p.add_argument("--copy-calibration", type=float, default=0.0,
@@ -57,6 +60,39 @@ def copy_calibration(mb):
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 5}))
 
 
+TRAFFIC_PROFILES = {2: "profiles/k_mortar_flux_ns_n5_plane128x64_traffic.md"}
+
+
+def measured_traffic(config, precision, tuning):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter
+    summary, or None when there is none for this workload, the kernel sources have
+    changed since the counters were taken, or the autotuner picked another launch."""
+    import hashlib
+    rel = TRAFFIC_PROFILES.get(config)
+    if rel is None or precision != "fp32" or not tuning:
+        return None
+    path = os.path.join(ROOT, rel)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith((" ", "#", "-", "|")):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    try:
+        h = hashlib.sha256()
+        for name in kv["sources"].split():
+            with open(os.path.join(ROOT, "paper_2008_04356_amd", "csrc", name), "rb") as fh:
+                h.update(fh.read())
+        t = dict(x.split("=") for x in kv["tuning"].split())
+        same_launch = all(int(t[k]) == tuning[0][k] for k in ("variant", "tile_len", "grid"))
+        if h.hexdigest() != kv["sources_sha256"] or not same_launch:
+            return None
+        return int(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError, OSError):
+        return None
+
+
 def algorithmic_bytes(spec):
     """Bytes one flux launch must move: every input value read once and every output
     value written once (per mortar point: (V_in + 5) values, V_in = 20 for NS, 5 Euler),
@@ -69,7 +105,8 @@ def algorithmic_bytes(spec):
     return total
 
 
-def run_leg(M, W, specs, disp, steps, warmup, rotate_bytes, graph=False, plain=False, tune=True):
+def run_leg(M, W, specs, disp, steps, warmup, rotate_bytes, graph=False, plain=False, tune=True,
+            tune_cache=None):
     """Times one precision of a workload.  plain: one handle (one launch) per interface
     instead of the batched persistent launch; graph: each stage replays a captured HIP
     graph instead of eager launches; tune: the library's autotuner picks each launch
@@ -115,7 +152,7 @@ def run_leg(M, W, specs, disp, steps, warmup, rotate_bytes, graph=False, plain=F
         for i, op in enumerate(ops):
             sel = [i] if plain else None
             op.update([disp(0)[i]] if plain else disp(0))
-            tuning += op.autotune(*args(sets[0], sel), reps=3)
+            tuning += op.autotune(*args(sets[0], sel), reps=3, cache=tune_cache)
         torch.cuda.synchronize()
         print(f"[bench] autotune {time.time() - t1:.2f} s: {tuning}", file=sys.stderr, flush=True)
 
@@ -123,6 +160,10 @@ def run_leg(M, W, specs, disp, steps, warmup, rotate_bytes, graph=False, plain=F
     if graph:
         ops[0].update(disp(0))
         graphs = [ops[0].graph(*args(per)) for per in sets]
+
+    # per-stage conservation residual sums (FP64, on the device, no synchronization)
+    cons_dev = [torch.zeros((1 if plain else len(specs), 5, 3), dtype=torch.float64, device="cuda")
+                for _ in ops]
 
     def step(k):
         per = sets[k % nsets]
@@ -136,6 +177,10 @@ def run_leg(M, W, specs, disp, steps, warmup, rotate_bytes, graph=False, plain=F
         else:
             ops[0].update(d)
             ops[0].flux(*args(per))
+        for i, op in enumerate(ops):
+            sel = [i] if plain else range(len(specs))
+            op.conservation_device([per[j]["Fs"] for j in sel], [per[j]["Fm"] for j in sel],
+                                   cons_dev[i])
 
     for k in range(warmup):
         step(k)
@@ -147,6 +192,8 @@ def run_leg(M, W, specs, disp, steps, warmup, rotate_bytes, graph=False, plain=F
     e1.record()
     torch.cuda.synchronize()
     ms_step = e0.elapsed_time(e1) / steps
+    cs = torch.cat(cons_dev).cpu().numpy()
+    step_cons_rel = float(np.max(np.abs(cs[:, :, 0] - cs[:, :, 1]) / cs[:, :, 2]))
 
     # the fused flux launch(es) alone, timed with HIP events on the stream they run on
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -192,6 +239,7 @@ def run_leg(M, W, specs, disp, steps, warmup, rotate_bytes, graph=False, plain=F
         "achieved_GBs": achieved,
         "frac": achieved / HBM_PEAK_GBS,
         "conservation_rel_residual": cons_rel,
+        "conservation_rel_residual_last_step": step_cons_rel,
         "rotated_sets": nsets,
         "tuning": tuning,
     }
@@ -239,13 +287,13 @@ def main():
     prec = {"fp32": W.FP32, "bf16": W.BF16_MFMA, "fp16": W.FP16_MFMA}[a.precision]
     specs32, disp = W.config(a.config, precision=prec)
     r32 = run_leg(M, W, specs32, disp, a.steps, a.warmup, a.rotate_bytes, graph=a.graph,
-                  tune=not a.no_autotune)
+                  tune=not a.no_autotune, tune_cache=a.tune_cache)
     r64 = None
     if not a.no_fp64:
         specs64, _ = W.config(a.config, precision=W.FP64)
         # the comparison point: plain FP64, one launch per interface
         r64 = run_leg(M, W, specs64, disp, a.steps, a.warmup, a.rotate_bytes, plain=True,
-                      tune=not a.no_autotune)
+                      tune=not a.no_autotune, tune_cache=a.tune_cache)
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(W, specs64 if r64 else specs32, disp, a.cpu_stages)
@@ -290,7 +338,8 @@ def main():
                                                        "conservation_rel_residual",
                                                        "rotated_sets", "tuning")}},
         "roofline": {"bound": "hbm", "achieved": r32["achieved_GBs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": r32["frac"], "traffic": None,
+                     "unit": "GB/s", "frac": r32["frac"],
+                     "traffic": measured_traffic(a.config, a.precision, r32["tuning"]),
                      "kernel": kname.get(a.config),
                      "bytes_per_launch": r32["bytes_per_launch"]},
         "cpu_baseline": cpu,

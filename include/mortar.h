@@ -207,6 +207,14 @@ int mortar_get_projection(mortar_handle *h, int iface, double *Pf, double *Pb);
 int mortar_conservation(mortar_handle *h, const void *const *F_s, const void *const *F_m,
                         double *out, void *stream);
 
+/* The same sums for every interface into a device array d_out [n_iface][5][3] (FP64),
+ * asynchronously on stream: no synchronization, no allocation, graph-capturable.  This
+ * is the per-stage form of the conservation residual (discrete conservation of the
+ * mortar projections, Sec. 3.2); each interface's scratch is reused, so calls on one
+ * handle must not overlap. */
+int mortar_conservation_device(mortar_handle *h, const void *const *F_s, const void *const *F_m,
+                               double *d_out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

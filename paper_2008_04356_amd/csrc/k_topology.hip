@@ -4,6 +4,8 @@
 //  - the device-side mortar sort (Sec. 4.4, Appendix A): sorted index array A and its
 //    inverse map m, rebuilt when the displacement crosses a whole face;
 //  - FP64 compensated conservation sums of the face fluxes of both sides.
+#include <algorithm>
+
 #include "assemble.h"
 #include "mortar_internal.h"
 
@@ -175,11 +177,13 @@ hipError_t launch_index_map(Iface &f, int side, hipStream_t st)
 }
 
 // ------------------------------------------------------------------------------------
-// Conservation sums (FP64, compensated).  Block b sums a fixed slice of the faces of
-// both sides; a second pass adds the block partials in a fixed order (deterministic).
+// Conservation sums (FP64, compensated).  Block (bx, p) sums point p of a fixed slice of
+// the faces of both sides for all five variables; the block's threads are combined by a
+// fixed shuffle tree and the partials of all blocks by one final pass in a fixed order,
+// so the result is deterministic.  Each accumulator is a Neumaier pair (sum, correction).
 // ------------------------------------------------------------------------------------
 
-struct Kahan {
+struct Neumaier {
     double s = 0.0, c = 0.0;
     __device__ void add(double x)
     {
@@ -187,49 +191,75 @@ struct Kahan {
         c += (fabs(s) >= fabs(x)) ? (s - t) + x : (x - t) + s;
         s = t;
     }
+    __device__ void merge(double os, double oc)
+    {
+        add(os);
+        c += oc;
+    }
 };
 
 template <typename T>
-__global__ void k_cons_partial(const T *__restrict__ Fs, const T *__restrict__ Fm,
-                               const int32_t *__restrict__ fid_s,
-                               const int32_t *__restrict__ fid_m,
-                               const BasisConsts *__restrict__ basis, int NP, int nfaces,
-                               int nfs, int nfm, double *__restrict__ part)
+__global__ __launch_bounds__(256) void k_cons_partial(const T *__restrict__ Fs,
+                                                      const T *__restrict__ Fm,
+                                                      const int32_t *__restrict__ fid_s,
+                                                      const int32_t *__restrict__ fid_m,
+                                                      const BasisConsts *__restrict__ basis,
+                                                      int NP, int nfaces, int nfs, int nfm,
+                                                      double *__restrict__ part)
 {
-    // part[blk][v][3][2] (sum and compensation)
-    __shared__ double red[256][2];
+    // part[block][v][3 sums][2]: static integral, moving integral, sum of |terms|
+    __shared__ double red[4][30];
     const int P = NP * NP;
-    for (int v = 0; v < 5; ++v) {
-        Kahan ks, km, ka;
-        for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < nfaces;
-             f += gridDim.x * blockDim.x) {
-            const int cs = fid_s[f], cm = fid_m[f];
-            for (int p = 0; p < P; ++p) {
-                const double w = basis->w[p % NP] * basis->w[p / NP];
-                const double a = w * (double)Fs[((size_t)v * P + p) * nfs + cs];
-                const double b = w * (double)Fm[((size_t)v * P + p) * nfm + cm];
-                ks.add(a);
-                km.add(b);
-                ka.add(fabs(a));
-                ka.add(fabs(b));
-            }
+    const int p = blockIdx.y;
+    const double w = basis->w[p % NP] * basis->w[p / NP];
+    Neumaier acc[5][3];
+    const size_t ps = (size_t)P * nfs, pm = (size_t)P * nfm;
+    for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < nfaces; f += gridDim.x * blockDim.x) {
+        const size_t os = (size_t)p * nfs + fid_s[f], om = (size_t)p * nfm + fid_m[f];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            const double x = w * (double)Fs[v * ps + os];
+            const double y = w * (double)Fm[v * pm + om];
+            acc[v][0].add(x);
+            acc[v][1].add(y);
+            acc[v][2].add(fabs(x));
+            acc[v][2].add(fabs(y));
         }
-        Kahan *acc[3] = {&ks, &km, &ka};
-        for (int c = 0; c < 3; ++c) {
-            red[threadIdx.x][0] = acc[c]->s;
-            red[threadIdx.x][1] = acc[c]->c;
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                Kahan t;
-                for (int i = 0; i < (int)blockDim.x; ++i) {
-                    t.add(red[i][0]);
-                    t.add(red[i][1]);
-                }
-                part[((size_t)blockIdx.x * 5 + v) * 6 + c * 2 + 0] = t.s;
-                part[((size_t)blockIdx.x * 5 + v) * 6 + c * 2 + 1] = t.c;
+    }
+    // wave tree (xor partners), then the four waves in order
+#pragma unroll
+    for (int m = 1; m < 64; m *= 2)
+#pragma unroll
+        for (int v = 0; v < 5; ++v)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double os = __shfl_xor(acc[v][c].s, m), oc = __shfl_xor(acc[v][c].c, m);
+                // both partners form the same pair sum: lower lane's value first
+                Neumaier t;
+                const bool lower = (threadIdx.x & m) == 0;
+                t.s = lower ? acc[v][c].s : os;
+                t.c = lower ? acc[v][c].c : oc;
+                t.merge(lower ? os : acc[v][c].s, lower ? oc : acc[v][c].c);
+                acc[v][c] = t;
             }
-            __syncthreads();
-        }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                red[wave][(v * 3 + c) * 2 + 0] = acc[v][c].s;
+                red[wave][(v * 3 + c) * 2 + 1] = acc[v][c].c;
+            }
+    }
+    __syncthreads();
+    if (threadIdx.x < 15) {
+        Neumaier t;
+        for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv)
+            t.merge(red[wv][threadIdx.x * 2 + 0], red[wv][threadIdx.x * 2 + 1]);
+        const size_t blk = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+        part[blk * 30 + threadIdx.x * 2 + 0] = t.s;
+        part[blk * 30 + threadIdx.x * 2 + 1] = t.c;
     }
 }
 
@@ -237,28 +267,32 @@ __global__ void k_cons_final(const double *__restrict__ part, int nblk, double *
 {
     const int e = threadIdx.x;  // (v, c)
     if (e >= 15) return;
-    const int v = e / 3, c = e % 3;
-    Kahan t;
-    for (int b = 0; b < nblk; ++b) {
-        t.add(part[((size_t)b * 5 + v) * 6 + c * 2 + 0]);
-        t.add(part[((size_t)b * 5 + v) * 6 + c * 2 + 1]);
-    }
-    out[v * 3 + c] = t.s + t.c;
+    Neumaier t;
+    for (int b = 0; b < nblk; ++b) t.merge(part[(size_t)b * 30 + e * 2 + 0], part[(size_t)b * 30 + e * 2 + 1]);
+    out[e] = t.s + t.c;
+}
+
+// Blocks along the faces for the conservation sums: about four faces per thread, at
+// most 64 (the point index is the second grid dimension).
+int cons_face_blocks(int nfaces)
+{
+    return std::max(1, std::min(64, (nfaces + 1023) / 1024));
 }
 
 hipError_t launch_conservation(const Iface &f, const void *Fs, const void *Fm, double *d_out,
                                hipStream_t st)
 {
-    const int nblk = f.n_cons_blocks;
+    const int nbx = cons_face_blocks(f.F);
+    const dim3 grid(nbx, f.P);
     if (f.d.precision == MORTAR_FP64)
-        hipLaunchKernelGGL(k_cons_partial<double>, dim3(nblk), dim3(256), 0, st,
+        hipLaunchKernelGGL(k_cons_partial<double>, grid, dim3(256), 0, st,
                            (const double *)Fs, (const double *)Fm, f.d_fid_s, f.d_fid_m,
                            f.d_basis, f.NP, f.F, f.d.n_face_static, f.d.n_face_moving, f.d_cons);
     else
-        hipLaunchKernelGGL(k_cons_partial<float>, dim3(nblk), dim3(256), 0, st,
+        hipLaunchKernelGGL(k_cons_partial<float>, grid, dim3(256), 0, st,
                            (const float *)Fs, (const float *)Fm, f.d_fid_s, f.d_fid_m,
                            f.d_basis, f.NP, f.F, f.d.n_face_static, f.d.n_face_moving, f.d_cons);
-    hipLaunchKernelGGL(k_cons_final, dim3(1), dim3(64), 0, st, f.d_cons, nblk, d_out);
+    hipLaunchKernelGGL(k_cons_final, dim3(1), dim3(64), 0, st, f.d_cons, nbx * f.P, d_out);
     return hipGetLastError();
 }
 

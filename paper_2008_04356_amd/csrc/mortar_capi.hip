@@ -261,7 +261,7 @@ static void free_iface(Iface &f)
 {
     void *bufs[] = {f.d_fid_s, f.d_fid_m, f.d_oid_s, f.d_oid_m, f.d_oval_s, f.d_oval_m,
                     f.d_metrics, f.d_params, f.d_basis, f.d_A[0], f.d_A[1], f.d_m[0],
-                    f.d_m[1], f.d_hist, f.d_cons};
+                    f.d_m[1], f.d_hist, f.d_cons, f.d_cons_out};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     f = Iface();
@@ -381,7 +381,8 @@ static int setup_one(const mortar_iface_desc &d, Iface &f)
         f.flux_occ = variant_occupancy(f, f.flux_variant);
         (void)ns; (void)met; (void)riem;
     }
-    f.n_cons_blocks = std::min(256, std::max(1, (f.F + 255) / 256));
+    f.n_cons_blocks = cons_face_blocks(f.F) * f.P;
+    if (hipMalloc((void **)&f.d_cons_out, sizeof(double) * 15) != hipSuccess) return MORTAR_ERR_OOM;
     if (hipMalloc((void **)&f.d_cons, sizeof(double) * 30 * (size_t)f.n_cons_blocks) != hipSuccess)
         return MORTAR_ERR_OOM;
     return MORTAR_OK;
@@ -631,28 +632,31 @@ int mortar_get_projection(mortar_handle *h, int iface, double *Pf, double *Pb)
     return MORTAR_OK;
 }
 
+int mortar_conservation_device(mortar_handle *h, const void *const *F_s, const void *const *F_m,
+                               double *d_out, void *stream)
+{
+    if (!h || !F_s || !F_m || !d_out) return MORTAR_ERR_INVALID_ARG;
+    for (size_t i = 0; i < h->ifs.size(); ++i)
+        if (!F_s[i] || !F_m[i]) return MORTAR_ERR_INVALID_ARG;
+    for (size_t i = 0; i < h->ifs.size(); ++i)
+        TRY_HIP(launch_conservation(h->ifs[i], F_s[i], F_m[i], d_out + 15 * i, (hipStream_t)stream));
+    return MORTAR_OK;
+}
+
 int mortar_conservation(mortar_handle *h, const void *const *F_s, const void *const *F_m,
                         double *out, void *stream)
 {
     if (!h || !F_s || !F_m || !out) return MORTAR_ERR_INVALID_ARG;
     hipStream_t st = (hipStream_t)stream;
-    const size_t n_if = h->ifs.size();
-    double *d_out = nullptr;
-    if (hipMalloc((void **)&d_out, sizeof(double) * 15 * n_if) != hipSuccess) return MORTAR_ERR_OOM;
-    int rc = MORTAR_OK;
-    for (size_t i = 0; i < n_if && rc == MORTAR_OK; ++i) {
-        if (!F_s[i] || !F_m[i]) rc = MORTAR_ERR_INVALID_ARG;
-        else if (launch_conservation(h->ifs[i], F_s[i], F_m[i], d_out + 15 * i, st) != hipSuccess)
-            rc = MORTAR_ERR_HIP;
+    for (size_t i = 0; i < h->ifs.size(); ++i) {
+        if (!F_s[i] || !F_m[i]) return MORTAR_ERR_INVALID_ARG;
+        const Iface &f = h->ifs[i];
+        TRY_HIP(launch_conservation(f, F_s[i], F_m[i], f.d_cons_out, st));
+        TRY_HIP(hipMemcpyAsync(out + 15 * i, f.d_cons_out, sizeof(double) * 15,
+                               hipMemcpyDeviceToHost, st));
     }
-    if (rc == MORTAR_OK) {
-        if (hipMemcpyAsync(out, d_out, sizeof(double) * 15 * n_if, hipMemcpyDeviceToHost, st) !=
-                hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess)
-            rc = MORTAR_ERR_HIP;
-    }
-    (void)hipFree(d_out);
-    return rc;
+    TRY_HIP(hipStreamSynchronize(st));
+    return MORTAR_OK;
 }
 
 int mortar_graph_create(mortar_handle *h, const void *const *U_s, const void *const *U_m,

@@ -67,7 +67,8 @@ struct Iface {
     double s = 0.0;
     int64_t nmod_built = -1;           // n mod n_par of the current index map
     bool ready = false;
-    double *d_cons = nullptr;          // conservation partials
+    double *d_cons = nullptr;          // conservation partials [blocks][30]
+    double *d_cons_out = nullptr;      // conservation sums [5][3] of the last host query
     int n_cons_blocks = 0;
     int flux_occ = 1;                  // resident flux workgroups per CU
     int flux_variant = 0;              // 0: VALU projections, 1: matrix-core projections
@@ -97,6 +98,7 @@ struct Handle;
 hipError_t launch_flux_batched(const Handle &h, const void *const *Us, const void *const *Um,
                                const void *const *Gs, const void *const *Gm, void *const *Fs,
                                void *const *Fm, hipStream_t st);
+int cons_face_blocks(int nfaces);
 hipError_t launch_conservation(const Iface &f, const void *Fs, const void *Fm, double *d_out,
                                hipStream_t st);
 

@@ -73,6 +73,7 @@ def _load():
     L.mortar_get_index_map.argtypes = [C.c_void_p, C.c_int, C.c_int, _ip, _ip]
     L.mortar_get_projection.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
     L.mortar_conservation.argtypes = [C.c_void_p, _vpp, _vpp, _dp, C.c_void_p]
+    L.mortar_conservation_device.argtypes = [C.c_void_p, _vpp, _vpp, C.c_void_p, C.c_void_p]
     L.mortar_graph_create.argtypes = [C.c_void_p, _vpp, _vpp, _vpp, _vpp, _vpp, _vpp,
                                       C.POINTER(C.c_void_p)]
     L.mortar_graph_launch.argtypes = [C.c_void_p, _dp, C.c_void_p]
@@ -159,6 +160,10 @@ def mortar_get_tuning(h, iface: int):
 def mortar_set_tuning(h, iface: int, variant: int, tile_len: int = 0, grid: int = 0) -> int:
     t = mortar_tuning(int(variant), int(tile_len), int(grid), 0)
     return lib.mortar_set_tuning(h, iface, C.byref(t))
+
+
+def mortar_conservation_device(h, Fs, Fm, d_out: int, stream: int = 0) -> int:
+    return lib.mortar_conservation_device(h, Fs, Fm, C.c_void_p(int(d_out)), C.c_void_p(stream))
 
 
 def mortar_destroy(h) -> int:
@@ -339,6 +344,12 @@ class MortarOperator:
     def graph(self, Us, Um, Gs, Gm, Fs, Fm):
         """Captures one stage for these fixed buffers; see MortarGraph."""
         return MortarGraph(self, Us, Um, Gs, Gm, Fs, Fm)
+
+    def conservation_device(self, Fs, Fm, out, stream=None):
+        """Asynchronous sums into the device tensor out (float64, [n_iface, 5, 3])."""
+        p = lambda ts: _ptrs([t.data_ptr() for t in ts])  # noqa: E731
+        _check(mortar_conservation_device(self.h, p(Fs), p(Fm), out.data_ptr(),
+                                          self._stream(stream)), "mortar_conservation_device")
 
     def conservation(self, Fs, Fm, stream=None):
         out = np.zeros((len(self.specs), 5, 3))

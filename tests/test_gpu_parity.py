@@ -178,6 +178,12 @@ def test_conservation_on_device(M, precision):
         # the device sums agree with the oracle's sums of the same arrays
         co = O.conservation(spec, outs[0][0].double().cpu().numpy(), outs[0][1].double().cpu().numpy())
         assert np.max(np.abs(c - co)) <= 1e-14 * np.max(np.abs(co))
+        # the asynchronous per-stage form writes the same sums into a device array
+        import torch
+        dev = torch.full((1, 5, 3), float("nan"), dtype=torch.float64, device="cuda:0")
+        op.conservation_device([outs[0][0]], [outs[0][1]], dev)
+        torch.cuda.synchronize()
+        assert np.array_equal(dev.cpu().numpy()[0], c)
     finally:
         op.close()
 
