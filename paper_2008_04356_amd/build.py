@@ -18,7 +18,7 @@ ARCH = os.environ.get("MORTAR_ARCH", "gfx950")
 
 SOURCES = ["mortar_capi.hip", "k_topology.hip", "k_flux_f32.hip", "k_flux_f64.hip",
            "k_flux_rd_f32.hip", "k_flux_rd_f64.hip", "k_flux_rd_bf16.hip",
-           "k_flux_rd_fp16.hip",
+           "k_flux_rd_fp16.hip", "k_flux_rd_batch_f32.hip",
            "k_flux_mfma_f32.hip", "k_flux_mfma_f64.hip", "k_flux_batch_f32.hip",
            "k_flux_batch_f64.hip"]
 
@@ -28,9 +28,16 @@ CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Wall", "-Wno-unused-function"]
 
 
+# The register-direct kernels keep matrix-core results in ordinary VGPRs (they feed the
+# vector units directly); not used for the FP64 unit.
+EXTRA = {s: ["-mllvm", "-amdgpu-mfma-vgpr-form"]
+         for s in ("k_flux_rd_f32.hip", "k_flux_rd_bf16.hip", "k_flux_rd_fp16.hip",
+                   "k_flux_rd_batch_f32.hip")}
+
+
 def _compile(src):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = ["hipcc", "-c", *CFLAGS, "-o", obj, os.path.join(CSRC, src)]
+    cmd = ["hipcc", "-c", *CFLAGS, *EXTRA.get(src, []), "-o", obj, os.path.join(CSRC, src)]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr[-6000:]}")

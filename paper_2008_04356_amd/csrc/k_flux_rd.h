@@ -20,7 +20,8 @@
 //
 // Precision (PREC): 0 runs the GEMMs in the element type (v_mfma_{f32,f64}_16x16x4).
 // 1 / 2 round the GEMM operands to bf16 / fp16 (v_mfma_f32_16x16x16_{bf16,f16}, FP32
-// accumulation; FP32 data).  The rounded matrices no longer integrate exactly, so the
+// accumulation; FP32 data; fp16 operands carry a power-of-two scale per wave, see
+// rd_fp16_scale).  The rounded matrices no longer integrate exactly, so the
 // back projection is then corrected per face line: with T the integral of the line's
 // mortar fluxes (sum of J_k w_q F, FP64 accumulation of FP32 fluxes) and A the integral
 // of the projected face flux (sum of w_j F_j), (T - A) / sum(w) is added to every node
@@ -173,6 +174,24 @@ template <> __device__ __forceinline__ void rd_store<double>(double x, const rd_
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(rd_u2, x), r, (int)off, soff, 0);
 }
 
+// fp16 operands: a power-of-two scale per wave and operand set keeps the values in the
+// normal range of fp16 (surface elements of fine meshes push fluxes below 6e-5, where
+// fp16 loses precision and then flushes to zero).  Scaling by powers of two is exact, so
+// the result is unscaled exactly afterwards.  Returns the scale for values of magnitude
+// up to m (the largest magnitude in this lane); maps the wave's largest into [1, 2).
+__device__ __forceinline__ float rd_fp16_scale(float m, float &inv)
+{
+#pragma unroll
+    for (int k = 1; k < 64; k <<= 1) m = fmaxf(m, __shfl_xor(m, k));
+    const int ex = (int)((__float_as_uint(m) >> 23) & 0xFF) - 127;
+    if (!(m > 0.0f) || ex > 126 || ex < -126) {   // zero, non-finite or extreme: no scaling
+        inv = 1.0f;
+        return 1.0f;
+    }
+    inv = __uint_as_float((uint32_t)(127 + ex) << 23);
+    return __uint_as_float((uint32_t)(127 - ex) << 23);
+}
+
 // Persistent schedule at wave granularity, with the XCD split of TileCursor: XCD x owns
 // the contiguous eighth of the tiles, and the waves of the workgroups on that XCD take
 // them in turn.  Requires gridDim.x >= min(8, n) so that every XCD's share has workers.
@@ -193,8 +212,11 @@ struct WaveCursor {
     __device__ void next() { k += stride; }
 };
 
+// One interface: every workgroup assembles the stage's matrices, then its waves take
+// tiles from the interface's wave cursor.  work: LDS of 8 NP^2 doubles; mats: 8 NP^2
+// element-type values; wq: NP doubles.  Contains __syncthreads (all threads call it).
 template <typename T, int NP, bool NSV, bool MET, int RIEM, int PREC>
-__global__ __launch_bounds__(256) void k_mortar_flux_rd(FluxArgs<T> a)
+__device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work, T *mats, double *wq)
 {
     using Op = RdOp<T, PREC>;
     using C = RdCfg<NP, NSV, MET, Op::KW>;
@@ -205,10 +227,6 @@ __global__ __launch_bounds__(256) void k_mortar_flux_rd(FluxArgs<T> a)
     constexpr int LF = KSF * E, LM = KSM * E;              // loaded values per lane and var
     static_assert(C::NT == 256, "launch bounds");
     static_assert(NP <= 16, "one 16-row block of face nodes in the back projection");
-
-    __shared__ double work[8 * NN];
-    __shared__ T mats[8 * NN];               // Pf[4][NP][NP], Pb[4][NP][NP]
-    __shared__ double wq[NP];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -375,6 +393,13 @@ __global__ __launch_bounds__(256) void k_mortar_flux_rd(FluxArgs<T> a)
         }
     };
     auto proj_s = [&](const T (&b)[LF], acc_t (&d)[RB]) {
+        float sc = 1.0f, inv = 1.0f;
+        if constexpr (PREC == 2) {
+            float m = 0.0f;
+#pragma unroll
+            for (int q = 0; q < LF; ++q) m = fmaxf(m, fabsf((float)b[q]));
+            sc = rd_fp16_scale(m, inv);
+        }
         op_t bo[KSF];
 #pragma unroll
         for (int ks = 0; ks < KSF; ++ks) {
@@ -382,7 +407,7 @@ __global__ __launch_bounds__(256) void k_mortar_flux_rd(FluxArgs<T> a)
             else {
                 float f[4];
 #pragma unroll
-                for (int e = 0; e < E; ++e) f[e] = (float)b[ks * E + e];
+                for (int e = 0; e < E; ++e) f[e] = (float)b[ks * E + e] * sc;
                 bo[ks] = Op::pack(f);
             }
         }
@@ -391,10 +416,21 @@ __global__ __launch_bounds__(256) void k_mortar_flux_rd(FluxArgs<T> a)
             acc_t acc = {0, 0, 0, 0};
 #pragma unroll
             for (int ks = 0; ks < KSF; ++ks) acc = Op::mma(Afs[rb][ks], bo[ks], acc);
+            if constexpr (PREC == 2) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[r] *= inv;
+            }
             d[rb] = acc;
         }
     };
     auto proj_m = [&](const T (&b)[LM], acc_t (&d)[RB]) {
+        float sc = 1.0f, inv = 1.0f;
+        if constexpr (PREC == 2) {
+            float m = 0.0f;     // the shifted values are other lanes' own values
+#pragma unroll
+            for (int q = 0; q < LM; ++q) m = fmaxf(m, fabsf((float)b[q]));
+            sc = rd_fp16_scale(m, inv);
+        }
         op_t bo[KSM];
 #pragma unroll
         for (int ks = 0; ks < KSM; ++ks) {
@@ -409,7 +445,7 @@ __global__ __launch_bounds__(256) void k_mortar_flux_rd(FluxArgs<T> a)
             else {
                 float f[4];
 #pragma unroll
-                for (int e = 0; e < E; ++e) f[e] = (float)x[e];
+                for (int e = 0; e < E; ++e) f[e] = (float)x[e] * sc;
                 bo[ks] = Op::pack(f);
             }
         }
@@ -418,45 +454,35 @@ __global__ __launch_bounds__(256) void k_mortar_flux_rd(FluxArgs<T> a)
             acc_t acc = {0, 0, 0, 0};
 #pragma unroll
             for (int ks = 0; ks < KSM; ++ks) acc = Op::mma(Afm[rb][ks], bo[ks], acc);
+            if constexpr (PREC == 2) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[r] *= inv;
+            }
             d[rb] = acc;
         }
     };
 
+    // Register budget: the waves hide each other's latency (two per SIMD for Navier-Stokes,
+    // more for Euler), so a tile keeps few values live.  The gradients of one side are
+    // projected only when its viscous flux is evaluated, and the pointwise fluxes of the
+    // lane's mortar nodes are evaluated one after the other: an empty asm statement that
+    // takes the previous node's flux and redefines the next node's inputs stops the
+    // compiler from interleaving all of them (which multiplies the live temporaries).
     WaveCursor cur(a.n_tiles, C::WAVES, wave);
-    if (!cur.valid()) return;
-    TileGeom g = tile_geom(a, cur.tile(), NP);
-    fetch_s(g);
-    fetch_m(g);
-    while (true) {
-        // The next tile's loads are issued as soon as the registers they fill are free:
-        // the static side after the static projections, the moving side after the
-        // moving ones, so that they fly while this tile's fluxes are evaluated.
-        acc_t QL[5][RB], QR[5][RB], MT[MET ? 4 : 1][RB], GL[NSV ? 15 : 1][RB], GR[NSV ? 15 : 1][RB];
+    for (; cur.valid(); cur.next()) {
+        const TileGeom gc = tile_geom(a, cur.tile(), NP);
+        fetch_s(gc);
+        fetch_m(gc);
+        acc_t QL[5][RB], QR[5][RB], MT[MET ? 4 : 1][RB];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) proj_s(ls[v], QL[v]);
+        for (int v = 0; v < 5; ++v) {
+            proj_s(ls[v], QL[v]);
+            proj_m(lm[v], QR[v]);
+        }
         if constexpr (MET) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) proj_s(ls[V + c], MT[c]);
         }
-        if constexpr (NSV) {
-#pragma unroll
-            for (int gg = 0; gg < 15; ++gg) proj_s(ls[5 + gg], GL[gg]);
-        }
-        cur.next();
-        const bool more = cur.valid();
-        const TileGeom gc = g;
-        if (more) {
-            g = tile_geom(a, cur.tile(), NP);
-            fetch_s(g);
-        }
-#pragma unroll
-        for (int v = 0; v < 5; ++v) proj_m(lm[v], QR[v]);
-        if constexpr (NSV) {
-#pragma unroll
-            for (int gg = 0; gg < 15; ++gg) proj_m(lm[5 + gg], GR[gg]);
-        }
-        if (more) fetch_m(g);
-
         // rows of this lane that are mortar nodes the tile needs: mortar (i0-1+col, 0)
         // for col >= 1, mortar (i0-1+col, 1) for every live column
         const bool live = col <= gc.nf;
@@ -468,46 +494,82 @@ __global__ __launch_bounds__(256) void k_mortar_flux_rd(FluxArgs<T> a)
                 const int rho = rrow[rb][r];
                 use[rb][r] = live && (rho < NP ? col >= 1 : rho < 2 * NP);
             }
-
+        auto normal = [&](int rb, int r, T &nx, T &ny, T &nz) {
+            nx = a.nx;
+            ny = a.ny;
+            nz = a.nz;
+            if constexpr (MET) {
+                nx = MT[0][rb][r];
+                ny = MT[1][rb][r];
+                nz = MT[2][rb][r];
+            }
+        };
         // ---- flux at the lane's mortar nodes --------------------------------------------
         // Rows that are not needed mortar nodes (padding rows, the halo column's first
         // mortar, columns past the tile) hold values that may be anything, even
         // non-finite; their fluxes are replaced by exact zeros below, and no other row or
         // column ever reads them.
         T FR[5][RB][4];
+        T Fprev[5] = {0, 0, 0, 0, 0};
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const bool u = use[rb][r];
-                T UL[5], UR[5], F[5];
+                T UL[5], UR[5], F[5], nx, ny, nz;
 #pragma unroll
                 for (int v = 0; v < 5; ++v) {
                     UL[v] = T(QL[v][rb][r]);
                     UR[v] = T(QR[v][rb][r]);
                 }
-                T nx = a.nx, ny = a.ny, nz = a.nz, dS = a.dS;
-                if constexpr (MET) {
-                    nx = MT[0][rb][r];
-                    ny = MT[1][rb][r];
-                    nz = MT[2][rb][r];
-                    dS = MT[3][rb][r];
-                }
+                if (rb + r > 0)
+                    asm volatile("" : "+v"(UL[0]), "+v"(UL[1]), "+v"(UL[2]), "+v"(UL[3]), "+v"(UL[4]),
+                                      "+v"(UR[0]), "+v"(UR[1]), "+v"(UR[2]), "+v"(UR[3]), "+v"(UR[4])
+                                    : "v"(Fprev[0]), "v"(Fprev[1]), "v"(Fprev[2]), "v"(Fprev[3]), "v"(Fprev[4]));
+                normal(rb, r, nx, ny, nz);
                 convective_flux<T, RIEM>(UL, UR, nx, ny, nz, a.gas, F);
-                if constexpr (NSV) {
-                    T G[15], FvL[5], FvR[5];
 #pragma unroll
-                    for (int gg = 0; gg < 15; ++gg) G[gg] = T(GL[gg][rb][r]);
-                    viscous_flux(UL, G, nx, ny, nz, a.gas, FvL);
+                for (int v = 0; v < 5; ++v) FR[v][rb][r] = Fprev[v] = F[v];
+            }
+        // BR1: minus half the viscous flux of each side, one side's gradients at a time
+        if constexpr (NSV) {
 #pragma unroll
-                    for (int gg = 0; gg < 15; ++gg) G[gg] = T(GR[gg][rb][r]);
-                    viscous_flux(UR, G, nx, ny, nz, a.gas, FvR);
+            for (int sd = 0; sd < 2; ++sd) {
+                acc_t GQ[15][RB];
 #pragma unroll
-                    for (int v = 0; v < 5; ++v) F[v] -= T(0.5) * (FvL[v] + FvR[v]);
+                for (int gg = 0; gg < 15; ++gg) {
+                    if (sd == 0) proj_s(ls[5 + gg], GQ[gg]);
+                    else proj_m(lm[5 + gg], GQ[gg]);
                 }
-                // rows that are not needed mortar nodes contribute nothing
 #pragma unroll
-                for (int v = 0; v < 5; ++v) FR[v][rb][r] = u ? F[v] * dS : T(0);
+                for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        T U[5], G[15], Fv[5], nx, ny, nz;
+#pragma unroll
+                        for (int v = 0; v < 5; ++v) U[v] = T(sd == 0 ? QL[v][rb][r] : QR[v][rb][r]);
+#pragma unroll
+                        for (int gg = 0; gg < 15; ++gg) G[gg] = T(GQ[gg][rb][r]);
+                        asm volatile("" : "+v"(G[0]), "+v"(G[1]), "+v"(G[2]), "+v"(G[3]), "+v"(G[4]),
+                                          "+v"(G[5]), "+v"(G[6]), "+v"(G[7]), "+v"(G[8]), "+v"(G[9]),
+                                          "+v"(G[10]), "+v"(G[11]), "+v"(G[12]), "+v"(G[13]),
+                                          "+v"(G[14]), "+v"(U[0]), "+v"(U[4])
+                                        : "v"(Fprev[1]), "v"(Fprev[2]), "v"(Fprev[3]), "v"(Fprev[4]));
+                        normal(rb, r, nx, ny, nz);
+                        viscous_flux(U, G, nx, ny, nz, a.gas, Fv);
+#pragma unroll
+                        for (int v = 1; v < 5; ++v) Fprev[v] = FR[v][rb][r] -= T(0.5) * Fv[v];
+                    }
+            }
+        }
+        // surface element; rows that are not needed mortar nodes contribute nothing
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                T dS = a.dS;
+                if constexpr (MET) dS = MT[3][rb][r];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) FR[v][rb][r] = use[rb][r] ? FR[v][rb][r] * dS : T(0);
             }
 
         // ---- back projection onto both sides ----------------------------------------
@@ -533,6 +595,15 @@ __global__ __launch_bounds__(256) void k_mortar_flux_rd(FluxArgs<T> a)
                     const T nxt = rd_right(FR[v][rb][r]);
                     FM[rb][r] = rrow[rb][r] < NP ? nxt : FR[v][rb][r];
                 }
+            float sc = 1.0f, inv = 1.0f;
+            if constexpr (PREC == 2) {
+                float m = 0.0f;    // FM holds values of this wave's FR
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) m = fmaxf(m, fabsf((float)FR[v][rb][r]));
+                sc = rd_fp16_scale(m, inv);
+            }
             acc_t ds = {0, 0, 0, 0}, dm = {0, 0, 0, 0};
 #pragma unroll
             for (int kb = 0; kb < KSB; ++kb) {
@@ -544,8 +615,8 @@ __global__ __launch_bounds__(256) void k_mortar_flux_rd(FluxArgs<T> a)
                     bsrc(kb, e, rb, r);
                     xs[e] = FR[v][rb][r];
                     xm[e] = FM[rb][r];
-                    fs[e] = (float)xs[e];
-                    fm[e] = (float)xm[e];
+                    fs[e] = (float)xs[e] * sc;
+                    fm[e] = (float)xm[e] * sc;
                 }
                 if constexpr (PREC == 0) {
                     ds = Op::mma(Abs[kb], Op::pack(xs), ds);
@@ -553,6 +624,13 @@ __global__ __launch_bounds__(256) void k_mortar_flux_rd(FluxArgs<T> a)
                 } else {
                     ds = Op::mma(Abs[kb], Op::pack(fs), ds);
                     dm = Op::mma(Abm[kb], Op::pack(fm), dm);
+                }
+            }
+            if constexpr (PREC == 2) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    ds[r] *= inv;
+                    dm[r] *= inv;
                 }
             }
             if constexpr (PREC != 0) {
@@ -598,7 +676,39 @@ __global__ __launch_bounds__(256) void k_mortar_flux_rd(FluxArgs<T> a)
                 }
             }
         }
-        if (!more) break;
+    }
+}
+
+template <typename T, int NP, bool NSV, bool MET, int RIEM, int PREC>
+__global__ __launch_bounds__(256) void k_mortar_flux_rd(FluxArgs<T> a)
+{
+    __shared__ double work[8 * NP * NP];
+    __shared__ T mats[8 * NP * NP];          // Pf[4][NP][NP], Pb[4][NP][NP]
+    __shared__ double wq[NP];
+    rd_interface<T, NP, NSV, MET, RIEM, PREC>(a, work, mats, wq);
+}
+
+// Every interface of a batch in one persistent launch (degrees N = 3, 5, 7, element type
+// FP32): the workgroups take the interfaces one after the other, each with its own
+// XCD-aware wave cursor.  The bodies are inlined; the host launches this kernel only
+// for batches whose degrees are all in {3, 5, 7}.
+template <bool NSV, int RIEM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_mortar_flux_rd_batch(BatchArgs<float> b)
+{
+    constexpr int NPM = 8;
+    __shared__ double work[8 * NPM * NPM];
+    __shared__ float mats[8 * NPM * NPM];
+    __shared__ double wq[NPM];
+    for (int i = 0; i < b.n_if; ++i) {
+        const bool met = b.met[i] != 0;
+#define MORTAR_RD_BATCH_NP(NPV)                                                               \
+    if (b.np[i] == NPV) {                                                                     \
+        if (met) rd_interface<float, NPV, NSV, true, RIEM, 0>(b.a[i], work, mats, wq);        \
+        else rd_interface<float, NPV, NSV, false, RIEM, 0>(b.a[i], work, mats, wq);           \
+        continue;                                                                             \
+    }
+        MORTAR_RD_BATCH_NP(4) MORTAR_RD_BATCH_NP(6) MORTAR_RD_BATCH_NP(8)
+#undef MORTAR_RD_BATCH_NP
     }
 }
 

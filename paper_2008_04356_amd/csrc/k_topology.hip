@@ -177,10 +177,10 @@ hipError_t launch_index_map(Iface &f, int side, hipStream_t st)
 }
 
 // ------------------------------------------------------------------------------------
-// Conservation sums (FP64, compensated).  Block (bx, p) sums point p of a fixed slice of
-// the faces of both sides for all five variables; the block's threads are combined by a
-// fixed shuffle tree and the partials of all blocks by one final pass in a fixed order,
-// so the result is deterministic.  Each accumulator is a Neumaier pair (sum, correction).
+// Conservation sums (FP64, compensated).  Each block sums a fixed set of (point, face)
+// elements of both sides for all five variables; the threads of a block and then the
+// block partials are combined by fixed LDS trees, so the result is deterministic.  Each
+// accumulator is a Neumaier pair (sum, correction).
 // ------------------------------------------------------------------------------------
 
 struct Neumaier {
@@ -198,6 +198,43 @@ struct Neumaier {
     }
 };
 
+// Deterministic in-block combination of 256 threads' Neumaier pairs for NV values: a
+// fixed halving tree in LDS.  Every thread must call it; the result is in thread 0.
+template <int NV>
+__device__ void cons_block_tree(Neumaier (&acc)[NV], double (*red)[256][2])
+{
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int e = 0; e < NV; ++e) {
+        red[e][t][0] = acc[e].s;
+        red[e][t][1] = acc[e].c;
+    }
+    __syncthreads();
+    for (int stride = 128; stride > 0; stride >>= 1) {
+        if (t < stride) {
+#pragma unroll
+            for (int e = 0; e < NV; ++e) {
+                Neumaier x;
+                x.s = red[e][t][0];
+                x.c = red[e][t][1];
+                x.merge(red[e][t + stride][0], red[e][t + stride][1]);
+                red[e][t][0] = x.s;
+                red[e][t][1] = x.c;
+            }
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+#pragma unroll
+        for (int e = 0; e < NV; ++e) {
+            acc[e].s = red[e][0][0];
+            acc[e].c = red[e][0][1];
+        }
+    }
+}
+
+// Block b sums a fixed set of (point, face) elements of both sides for all five
+// variables: element k = p * nfaces + f, k = b*256 + t + j*gridDim*256.
 template <typename T>
 __global__ __launch_bounds__(256) void k_cons_partial(const T *__restrict__ Fs,
                                                       const T *__restrict__ Fm,
@@ -207,83 +244,81 @@ __global__ __launch_bounds__(256) void k_cons_partial(const T *__restrict__ Fs,
                                                       int NP, int nfaces, int nfs, int nfm,
                                                       double *__restrict__ part)
 {
-    // part[block][v][3 sums][2]: static integral, moving integral, sum of |terms|
-    __shared__ double red[4][30];
+    // part[block][v * 3 + sum][2]: sums = static integral, moving integral, sum of |terms|
+    __shared__ double red[15][256][2];
+    __shared__ double wq[kMaxNP * kMaxNP];
     const int P = NP * NP;
-    const int p = blockIdx.y;
-    const double w = basis->w[p % NP] * basis->w[p / NP];
-    Neumaier acc[5][3];
+    for (int p = threadIdx.x; p < P; p += blockDim.x) wq[p] = basis->w[p % NP] * basis->w[p / NP];
+    __syncthreads();
+    Neumaier acc[15];
     const size_t ps = (size_t)P * nfs, pm = (size_t)P * nfm;
-    for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < nfaces; f += gridDim.x * blockDim.x) {
-        const size_t os = (size_t)p * nfs + fid_s[f], om = (size_t)p * nfm + fid_m[f];
+    const int64_t total = (int64_t)P * nfaces;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k0 < total; k0 += 4 * stride) {
+        // four elements per pass: their loads are all issued before the first add
+        T xs[4][5], ys[4][5];
+        double w[4];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) {
-            const double x = w * (double)Fs[v * ps + os];
-            const double y = w * (double)Fm[v * pm + om];
-            acc[v][0].add(x);
-            acc[v][1].add(y);
-            acc[v][2].add(fabs(x));
-            acc[v][2].add(fabs(y));
+        for (int u = 0; u < 4; ++u) {
+            const int64_t k = k0 + u * stride;
+            const bool ok = k < total;
+            const int p = ok ? (int)(k / nfaces) : 0, f = ok ? (int)(k - (int64_t)p * nfaces) : 0;
+            w[u] = ok ? wq[p] : 0.0;
+            const size_t os = (size_t)p * nfs + fid_s[f], om = (size_t)p * nfm + fid_m[f];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                xs[u][v] = Fs[v * ps + os];
+                ys[u][v] = Fm[v * pm + om];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                const double x = w[u] * (double)xs[u][v];
+                const double y = w[u] * (double)ys[u][v];
+                acc[v * 3 + 0].add(x);
+                acc[v * 3 + 1].add(y);
+                acc[v * 3 + 2].add(fabs(x) + fabs(y));
+            }
+    }
+    cons_block_tree<15>(acc, red);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int e = 0; e < 15; ++e) {
+            part[(size_t)blockIdx.x * 30 + e * 2 + 0] = acc[e].s;
+            part[(size_t)blockIdx.x * 30 + e * 2 + 1] = acc[e].c;
         }
     }
-    // wave tree (xor partners), then the four waves in order
-#pragma unroll
-    for (int m = 1; m < 64; m *= 2)
-#pragma unroll
-        for (int v = 0; v < 5; ++v)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const double os = __shfl_xor(acc[v][c].s, m), oc = __shfl_xor(acc[v][c].c, m);
-                // both partners form the same pair sum: lower lane's value first
-                Neumaier t;
-                const bool lower = (threadIdx.x & m) == 0;
-                t.s = lower ? acc[v][c].s : os;
-                t.c = lower ? acc[v][c].c : oc;
-                t.merge(lower ? os : acc[v][c].s, lower ? oc : acc[v][c].c);
-                acc[v][c] = t;
-            }
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane == 0) {
-#pragma unroll
-        for (int v = 0; v < 5; ++v)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                red[wave][(v * 3 + c) * 2 + 0] = acc[v][c].s;
-                red[wave][(v * 3 + c) * 2 + 1] = acc[v][c].c;
-            }
-    }
-    __syncthreads();
-    if (threadIdx.x < 15) {
-        Neumaier t;
-        for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv)
-            t.merge(red[wv][threadIdx.x * 2 + 0], red[wv][threadIdx.x * 2 + 1]);
-        const size_t blk = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
-        part[blk * 30 + threadIdx.x * 2 + 0] = t.s;
-        part[blk * 30 + threadIdx.x * 2 + 1] = t.c;
-    }
 }
 
-__global__ void k_cons_final(const double *__restrict__ part, int nblk, double *__restrict__ out)
+__global__ __launch_bounds__(256) void k_cons_final(const double *__restrict__ part, int nblk,
+                                                    double *__restrict__ out)
 {
-    const int e = threadIdx.x;  // (v, c)
-    if (e >= 15) return;
-    Neumaier t;
-    for (int b = 0; b < nblk; ++b) t.merge(part[(size_t)b * 30 + e * 2 + 0], part[(size_t)b * 30 + e * 2 + 1]);
-    out[e] = t.s + t.c;
+    __shared__ double red[15][256][2];
+    Neumaier acc[15];
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+#pragma unroll
+        for (int e = 0; e < 15; ++e) acc[e].merge(part[(size_t)b * 30 + e * 2 + 0], part[(size_t)b * 30 + e * 2 + 1]);
+    cons_block_tree<15>(acc, red);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int e = 0; e < 15; ++e) out[e] = acc[e].s + acc[e].c;
 }
 
-// Blocks along the faces for the conservation sums: about four faces per thread, at
-// most 64 (the point index is the second grid dimension).
-int cons_face_blocks(int nfaces)
+// Blocks of the conservation sums: about four (point, face) elements per thread, at
+// most 2048 blocks.
+int cons_blocks(int P, int nfaces)
 {
-    return std::max(1, std::min(64, (nfaces + 1023) / 1024));
+    const int64_t total = (int64_t)P * nfaces;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(2048, (total + 1023) / 1024));
 }
 
 hipError_t launch_conservation(const Iface &f, const void *Fs, const void *Fm, double *d_out,
                                hipStream_t st)
 {
-    const int nbx = cons_face_blocks(f.F);
-    const dim3 grid(nbx, f.P);
+    const int nblk = cons_blocks(f.P, f.F);
+    const dim3 grid(nblk);
     if (f.d.precision == MORTAR_FP64)
         hipLaunchKernelGGL(k_cons_partial<double>, grid, dim3(256), 0, st,
                            (const double *)Fs, (const double *)Fm, f.d_fid_s, f.d_fid_m,
@@ -292,7 +327,7 @@ hipError_t launch_conservation(const Iface &f, const void *Fs, const void *Fm, d
         hipLaunchKernelGGL(k_cons_partial<float>, grid, dim3(256), 0, st,
                            (const float *)Fs, (const float *)Fm, f.d_fid_s, f.d_fid_m,
                            f.d_basis, f.NP, f.F, f.d.n_face_static, f.d.n_face_moving, f.d_cons);
-    hipLaunchKernelGGL(k_cons_final, dim3(1), dim3(64), 0, st, f.d_cons, nbx * f.P, d_out);
+    hipLaunchKernelGGL(k_cons_final, dim3(1), dim3(256), 0, st, f.d_cons, nblk, d_out);
     return hipGetLastError();
 }
 

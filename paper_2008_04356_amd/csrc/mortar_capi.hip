@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <cstdio>
 #include <cstdlib>
 #include <new>
 #include <string>
@@ -31,6 +32,9 @@ hipError_t launch_flux_batch_f32(const BatchArgs<float> &b, int grid, bool ns, i
 hipError_t launch_flux_batch_f64(const BatchArgs<double> &b, int grid, bool ns, int riem,
                                  bool turbine, hipStream_t st);
 int flux_batch_occupancy_f32(bool ns, int riem, bool turbine);
+int flux_rd_batch_occupancy_f32(bool ns, int riem);
+hipError_t launch_flux_rd_batch_f32(const BatchArgs<float> &b, int grid, bool ns, int riem,
+                                    hipStream_t st);
 int flux_rd_occupancy_f32(int NP, bool ns, bool met, int riem);
 int flux_rd_occupancy_f64(int NP, bool ns, bool met, int riem);
 int flux_rd_occupancy_bf16(int NP, bool ns, bool met, int riem);
@@ -381,7 +385,7 @@ static int setup_one(const mortar_iface_desc &d, Iface &f)
         f.flux_occ = variant_occupancy(f, f.flux_variant);
         (void)ns; (void)met; (void)riem;
     }
-    f.n_cons_blocks = cons_face_blocks(f.F) * f.P;
+    f.n_cons_blocks = cons_blocks(f.P, f.F);
     if (hipMalloc((void **)&f.d_cons_out, sizeof(double) * 15) != hipSuccess) return MORTAR_ERR_OOM;
     if (hipMalloc((void **)&f.d_cons, sizeof(double) * 30 * (size_t)f.n_cons_blocks) != hipSuccess)
         return MORTAR_ERR_OOM;
@@ -533,6 +537,11 @@ int mortar_setup(const mortar_iface_desc *desc, int n_iface, mortar_handle **out
         if (same)
             h->batch_occ = f0.elem == 8 ? flux_batch_occupancy_f64(ns, riem, h->batch_turbine)
                                         : flux_batch_occupancy_f32(ns, riem, h->batch_turbine);
+        // the register-direct batch kernel: FP32, degrees N = 3, 5, 7
+        bool rd_ok = same && f0.elem == 4;
+        for (const Iface &f : h->ifs) rd_ok = rd_ok && f.lp == 0 && variant_allowed(f, 2);
+        h->batch_rd_ok = rd_ok && turbine;
+        if (h->batch_rd_ok) h->batch_occ_rd = flux_rd_batch_occupancy_f32(ns, riem);
     }
     *out = h;
     return MORTAR_OK;
@@ -839,28 +848,63 @@ int mortar_autotune(mortar_handle *h, const void *const *U_s, const void *const 
     }
     h->tune_epoch++;
     float ms = 0.f;
+    // MORTAR_TUNE_LOG=1 prints every candidate's time to stderr
+    const bool log = std::getenv("MORTAR_TUNE_LOG") != nullptr;
+    auto note = [&](int iface, int v, int t, int g) {
+        if (log) std::fprintf(stderr, "[autotune] iface %d variant %d tile %d grid %d: %.2f us\n", iface, v, t, g, 1e3 * ms);
+    };
     if (h->batched) {
         auto run = [&]() { return launch_flux_batched(*h, U_s, U_m, G_s, G_m, F_s, F_m, st); };
-        // coordinate descent: each interface's tile length, then the grid
-        for (size_t i = 0; i < n_if; ++i) {
-            Iface &f = h->ifs[i];
-            int best_t = f.tune_tile;
-            float best = 1e30f;
-            for (int t : tile_candidates(vmax_tile(f, 0))) {
-                f.tune_tile = t;
-                TRY_HIP(time_launches(run, reps, st, ms));
-                if (ms < best) { best = ms; best_t = t; }
+        auto set_variant = [&](int v) {
+            h->batch_variant = v;
+            for (Iface &f : h->ifs) {
+                f.flux_variant = v;
+                f.flux_occ = variant_occupancy(f, v);
             }
-            f.tune_tile = best_t;
+        };
+        // per batch kernel: coordinate descent over each interface's tile length, then
+        // the grid; keep the best batch kernel with its settings
+        float best_all = 1e30f;
+        int best_v = 0, best_grid = 0;
+        std::vector<int> best_tiles(n_if, 0);
+        for (int v : {0, 2}) {
+            if (v == 2 && !h->batch_rd_ok) continue;
+            set_variant(v);
+            h->tune_grid_batch = 0;
+            for (Iface &f : h->ifs) f.tune_tile = 0;
+            float best = 1e30f;
+            for (size_t i = 0; i < n_if; ++i) {
+                Iface &f = h->ifs[i];
+                int best_t = 0;
+                float bi = 1e30f;
+                for (int t : tile_candidates(vmax_tile(f, v))) {
+                    f.tune_tile = t;
+                    TRY_HIP(time_launches(run, reps, st, ms));
+                    note((int)i, v, t, h->tune_grid_batch);
+                    if (ms < bi) { bi = ms; best_t = t; }
+                }
+                f.tune_tile = best_t;
+            }
+            const int occ = v == 2 ? h->batch_occ_rd : h->batch_occ;
+            int best_g = 0;
+            float bg = 1e30f;
+            for (int k = occ; k >= 1; --k) {
+                h->tune_grid_batch = k == occ ? 0 : k * h->n_cu;
+                TRY_HIP(time_launches(run, reps, st, ms));
+                note(-1, v, 0, h->tune_grid_batch);
+                if (ms < bg) { bg = ms; best_g = h->tune_grid_batch; }
+            }
+            best = bg;
+            if (best < best_all) {
+                best_all = best;
+                best_v = v;
+                best_grid = best_g;
+                for (size_t i = 0; i < n_if; ++i) best_tiles[i] = h->ifs[i].tune_tile;
+            }
         }
-        int best_g = 0;
-        float best = 1e30f;
-        for (int k = h->batch_occ; k >= 1; --k) {
-            h->tune_grid_batch = k == h->batch_occ ? 0 : k * h->n_cu;
-            TRY_HIP(time_launches(run, reps, st, ms));
-            if (ms < best) { best = ms; best_g = h->tune_grid_batch; }
-        }
-        h->tune_grid_batch = best_g;
+        set_variant(best_v);
+        h->tune_grid_batch = best_grid;
+        for (size_t i = 0; i < n_if; ++i) h->ifs[i].tune_tile = best_tiles[i];
         return MORTAR_OK;
     }
     for (size_t i = 0; i < n_if; ++i) {
@@ -880,6 +924,7 @@ int mortar_autotune(mortar_handle *h, const void *const *U_s, const void *const 
             for (int t : tile_candidates(vmax_tile(f, v))) {
                 f.tune_tile = t;
                 TRY_HIP(time_launches(run, reps, st, ms));
+                note((int)i, v, t, 0);
                 if (ms < best) { best = ms; best_v = v; best_t = t; }
             }
         }
@@ -894,7 +939,7 @@ int mortar_get_tuning(const mortar_handle *h, int iface, mortar_tuning *out)
 {
     if (!h || !out || iface < 0 || iface >= (int)h->ifs.size()) return MORTAR_ERR_INVALID_ARG;
     const Iface &f = h->ifs[iface];
-    out->variant = f.flux_variant;
+    out->variant = h->batched ? h->batch_variant : f.flux_variant;
     out->tile_len = f.tune_tile;
     out->grid = h->batched ? h->tune_grid_batch : f.tune_grid;
     out->reserved = 0;
@@ -907,13 +952,23 @@ int mortar_set_tuning(mortar_handle *h, int iface, const mortar_tuning *t)
     if (t->tile_len < 0 || t->grid < 0 || (t->grid > 0 && t->grid < 8)) return MORTAR_ERR_INVALID_ARG;
     Iface &f = h->ifs[iface];
     if (!variant_allowed(f, t->variant)) return MORTAR_ERR_INVALID_ARG;
-    if (h->batched && t->variant != 0) return MORTAR_ERR_INVALID_ARG;
+    if (h->batched && !(t->variant == 0 || (t->variant == 2 && h->batch_rd_ok)))
+        return MORTAR_ERR_INVALID_ARG;
     h->tune_epoch++;
-    f.flux_variant = t->variant;
-    f.flux_occ = variant_occupancy(f, t->variant);
+    if (h->batched) {
+        // the kernel variant and the grid belong to the whole batch
+        h->batch_variant = t->variant;
+        for (Iface &g : h->ifs) {
+            g.flux_variant = t->variant;
+            g.flux_occ = variant_occupancy(g, t->variant);
+        }
+        h->tune_grid_batch = t->grid;
+    } else {
+        f.flux_variant = t->variant;
+        f.flux_occ = variant_occupancy(f, t->variant);
+        f.tune_grid = t->grid;
+    }
     f.tune_tile = t->tile_len;
-    if (h->batched) h->tune_grid_batch = t->grid;
-    else f.tune_grid = t->grid;
     return MORTAR_OK;
 }
 
@@ -1034,6 +1089,14 @@ hipError_t launch_flux_batched(const Handle &h, const void *const *Us, const voi
         if (h.tune_grid_batch > 0) return std::max(std::min(8, nt), std::min(nt, h.tune_grid_batch));
         return std::max(1, std::min(nt, h.batch_occ * h.n_cu));
     };
+    if (h.batch_variant == 2) {
+        // one tile per wave, four waves per workgroup; at least one workgroup per XCD
+        BatchArgs<float> b;
+        build(b);
+        const int grid = h.tune_grid_batch > 0 ? std::max(8, h.tune_grid_batch)
+                                               : std::max(8, std::min((total + 3) / 4, h.batch_occ_rd * h.n_cu));
+        return launch_flux_rd_batch_f32(b, grid, ns, riem, st);
+    }
     if (f0.elem == 8) {
         BatchArgs<double> b;
         build(b);

@@ -85,6 +85,9 @@ struct Handle {
     bool batch_turbine = false;        // the N = 3, 5, 7 instantiation covers the batch
     int batch_occ = 1;
     int tune_grid_batch = 0;           // workgroups of the batched launch (0: default)
+    int batch_variant = 0;             // batched kernel: 0 VALU projections, 2 register-direct
+    bool batch_rd_ok = false;          // the register-direct batch kernel covers the batch
+    int batch_occ_rd = 1;
     unsigned tune_epoch = 0;           // bumped by every tuning change
     std::vector<Iface> ifs;
 };
@@ -98,7 +101,7 @@ struct Handle;
 hipError_t launch_flux_batched(const Handle &h, const void *const *Us, const void *const *Um,
                                const void *const *Gs, const void *const *Gm, void *const *Fs,
                                void *const *Fm, hipStream_t st);
-int cons_face_blocks(int nfaces);
+int cons_blocks(int P, int nfaces);
 hipError_t launch_conservation(const Iface &f, const void *Fs, const void *Fm, double *d_out,
                                hipStream_t st);
 
