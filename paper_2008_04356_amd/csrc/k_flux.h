@@ -56,6 +56,8 @@ constexpr int kXcds = 8;   // MI355X: workgroups are dispatched round-robin over
 // LDS budget per workgroup of the VALU-projection kernel: 48 KB in FP32 (three
 // workgroups per CU), 80 KB in FP64 (two).
 template <typename T> constexpr int lds_budget() { return sizeof(T) == 8 ? 81920 : 49152; }
+// The wide-tile FP32 instantiation: 72 KB, two workgroups per CU.
+constexpr int kLdsWideF32 = 73728;
 
 // Degree sets of the batched kernel: every degree, or the 1.5-stage turbine set N = 3, 5, 7.
 constexpr int kMaskAll = 0x7FC;
@@ -94,7 +96,8 @@ constexpr size_t tile_lds(int tf)
 }
 
 // Tile capacity: among the capacities whose LDS fits the budget, the one that best fills
-// the 256-thread rounds of the flux phase, weighted by the halo overhead 1/(tf+1).
+// the 256-thread rounds of the flux phase, weighted by the halo overhead 1/(tf+1); or,
+// for the wide-tile budget, simply the longest (per-tile costs dominate there).
 template <typename T, int NP, int VS, int VM>
 constexpr int pick_tile(int budget)
 {
@@ -104,7 +107,8 @@ constexpr int pick_tile(int budget)
         if (tile_lds<T, NP, VS, VM>(tf) > (size_t)budget) break;
         const int pts = (2 * tf + 1) * NP;
         const int rounds = (pts + kFluxThreads - 1) / kFluxThreads;
-        const double score = (double)pts / (rounds * kFluxThreads) * tf / (tf + 1.0);
+        const double score = budget == kLdsWideF32 ? (double)tf
+                                                   : (double)pts / (rounds * kFluxThreads) * tf / (tf + 1.0);
         if (score > best_score + 1e-9) {
             best_score = score;
             best = tf;

@@ -1,0 +1,17 @@
+// Instantiations of the VALU mortar-flux kernel, element type float, 72 KB of LDS per
+// workgroup: longer tiles (less halo work per face) at two workgroups per CU.
+#include "k_flux_valu_launch.h"
+
+namespace mortar {
+
+using L = ValuLaunch<float, kLdsWideF32>;
+
+int flux_wide_occupancy_f32(int NP, bool ns, bool met, int riem) { return L::occupancy(NP, ns, met, riem); }
+int flux_wide_tile_capacity_f32(int NP, bool ns, bool met) { return L::capacity(NP, ns, met); }
+hipError_t launch_flux_wide_f32(const FluxArgs<float> &a, int NP, int grid, bool ns, bool met,
+                                int riem, hipStream_t st)
+{
+    return L::launch(a, NP, grid, ns, met, riem, st);
+}
+
+}  // namespace mortar

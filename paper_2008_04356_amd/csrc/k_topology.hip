@@ -178,9 +178,9 @@ hipError_t launch_index_map(Iface &f, int side, hipStream_t st)
 
 // ------------------------------------------------------------------------------------
 // Conservation sums (FP64, compensated).  Each block sums a fixed set of (point, face)
-// elements of both sides for all five variables; the threads of a block and then the
-// block partials are combined by fixed LDS trees, so the result is deterministic.  Each
-// accumulator is a Neumaier pair (sum, correction).
+// elements of one variable on one side; the threads of a block and then the block
+// partials are combined in fixed orders (xor trees within waves, waves in sequence), so
+// the result is deterministic.  Each accumulator is a Neumaier pair (sum, correction).
 // ------------------------------------------------------------------------------------
 
 struct Neumaier {
@@ -198,43 +198,26 @@ struct Neumaier {
     }
 };
 
-// Deterministic in-block combination of 256 threads' Neumaier pairs for NV values: a
-// fixed halving tree in LDS.  Every thread must call it; the result is in thread 0.
-template <int NV>
-__device__ void cons_block_tree(Neumaier (&acc)[NV], double (*red)[256][2])
+// Combination of a wave's Neumaier pairs by a fixed xor tree (both partners form the
+// same sum, lower lane first), so every lane ends with the wave's total.
+__device__ __forceinline__ Neumaier cons_wave_sum(Neumaier x)
 {
-    const int t = threadIdx.x;
 #pragma unroll
-    for (int e = 0; e < NV; ++e) {
-        red[e][t][0] = acc[e].s;
-        red[e][t][1] = acc[e].c;
+    for (int m = 1; m < 64; m <<= 1) {
+        const double os = __shfl_xor(x.s, m), oc = __shfl_xor(x.c, m);
+        const bool lower = (threadIdx.x & m) == 0;
+        Neumaier t;
+        t.s = lower ? x.s : os;
+        t.c = lower ? x.c : oc;
+        t.merge(lower ? os : x.s, lower ? oc : x.c);
+        x = t;
     }
-    __syncthreads();
-    for (int stride = 128; stride > 0; stride >>= 1) {
-        if (t < stride) {
-#pragma unroll
-            for (int e = 0; e < NV; ++e) {
-                Neumaier x;
-                x.s = red[e][t][0];
-                x.c = red[e][t][1];
-                x.merge(red[e][t + stride][0], red[e][t + stride][1]);
-                red[e][t][0] = x.s;
-                red[e][t][1] = x.c;
-            }
-        }
-        __syncthreads();
-    }
-    if (t == 0) {
-#pragma unroll
-        for (int e = 0; e < NV; ++e) {
-            acc[e].s = red[e][0][0];
-            acc[e].c = red[e][0][1];
-        }
-    }
+    return x;
 }
 
-// Block b sums a fixed set of (point, face) elements of both sides for all five
-// variables: element k = p * nfaces + f, k = b*256 + t + j*gridDim*256.
+// Partial sums: block (b, v, side) sums w_p w_q F and w_p w_q |F| of variable v on one
+// side over the (point, face) elements k = p * nfaces + f, k = b*256 + t + j*nb*256.
+// part[(v * 2 + side) * nb + b][2 pairs][2].
 template <typename T>
 __global__ __launch_bounds__(256) void k_cons_partial(const T *__restrict__ Fs,
                                                       const T *__restrict__ Fm,
@@ -244,81 +227,101 @@ __global__ __launch_bounds__(256) void k_cons_partial(const T *__restrict__ Fs,
                                                       int NP, int nfaces, int nfs, int nfm,
                                                       double *__restrict__ part)
 {
-    // part[block][v * 3 + sum][2]: sums = static integral, moving integral, sum of |terms|
-    __shared__ double red[15][256][2];
     __shared__ double wq[kMaxNP * kMaxNP];
+    __shared__ double red[4][2][2];
     const int P = NP * NP;
     for (int p = threadIdx.x; p < P; p += blockDim.x) wq[p] = basis->w[p % NP] * basis->w[p / NP];
     __syncthreads();
-    Neumaier acc[15];
-    const size_t ps = (size_t)P * nfs, pm = (size_t)P * nfm;
+    const int v = blockIdx.y, side = blockIdx.z;
+    const T *F = (side ? Fm : Fs) + (size_t)v * P * (side ? nfm : nfs);
+    const int32_t *fid = side ? fid_m : fid_s;
+    const int nf = side ? nfm : nfs;
+    Neumaier sum, mag;
     const int64_t total = (int64_t)P * nfaces;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t k0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k0 < total; k0 += 4 * stride) {
-        // four elements per pass: their loads are all issued before the first add
-        T xs[4][5], ys[4][5];
+        T x[4];
         double w[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 4; ++u) {       // the four loads are issued before the adds
             const int64_t k = k0 + u * stride;
             const bool ok = k < total;
             const int p = ok ? (int)(k / nfaces) : 0, f = ok ? (int)(k - (int64_t)p * nfaces) : 0;
             w[u] = ok ? wq[p] : 0.0;
-            const size_t os = (size_t)p * nfs + fid_s[f], om = (size_t)p * nfm + fid_m[f];
-#pragma unroll
-            for (int v = 0; v < 5; ++v) {
-                xs[u][v] = Fs[v * ps + os];
-                ys[u][v] = Fm[v * pm + om];
-            }
+            x[u] = F[(size_t)p * nf + fid[f]];
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int v = 0; v < 5; ++v) {
-                const double x = w[u] * (double)xs[u][v];
-                const double y = w[u] * (double)ys[u][v];
-                acc[v * 3 + 0].add(x);
-                acc[v * 3 + 1].add(y);
-                acc[v * 3 + 2].add(fabs(x) + fabs(y));
-            }
+        for (int u = 0; u < 4; ++u) {
+            const double y = w[u] * (double)x[u];
+            sum.add(y);
+            mag.add(fabs(y));
+        }
     }
-    cons_block_tree<15>(acc, red);
+    sum = cons_wave_sum(sum);
+    mag = cons_wave_sum(mag);
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[wave][0][0] = sum.s;
+        red[wave][0][1] = sum.c;
+        red[wave][1][0] = mag.s;
+        red[wave][1][1] = mag.c;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-#pragma unroll
-        for (int e = 0; e < 15; ++e) {
-            part[(size_t)blockIdx.x * 30 + e * 2 + 0] = acc[e].s;
-            part[(size_t)blockIdx.x * 30 + e * 2 + 1] = acc[e].c;
+        Neumaier a, m;
+        for (int w2 = 0; w2 < (int)(blockDim.x >> 6); ++w2) {
+            a.merge(red[w2][0][0], red[w2][0][1]);
+            m.merge(red[w2][1][0], red[w2][1][1]);
         }
+        double *o = part + (((size_t)v * 2 + side) * gridDim.x + blockIdx.x) * 4;
+        o[0] = a.s;
+        o[1] = a.c;
+        o[2] = m.s;
+        o[3] = m.c;
     }
 }
 
-__global__ __launch_bounds__(256) void k_cons_final(const double *__restrict__ part, int nblk,
+// Final pass: wave (v, side) adds its nb partials in a fixed order (xor tree); then
+// out[v][0] = static integral, out[v][1] = moving integral, out[v][2] = sum of |terms|.
+__global__ __launch_bounds__(640) void k_cons_final(const double *__restrict__ part, int nb,
                                                     double *__restrict__ out)
 {
-    __shared__ double red[15][256][2];
-    Neumaier acc[15];
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x)
-#pragma unroll
-        for (int e = 0; e < 15; ++e) acc[e].merge(part[(size_t)b * 30 + e * 2 + 0], part[(size_t)b * 30 + e * 2 + 1]);
-    cons_block_tree<15>(acc, red);
-    if (threadIdx.x == 0)
-#pragma unroll
-        for (int e = 0; e < 15; ++e) out[e] = acc[e].s + acc[e].c;
+    __shared__ double res[10][2];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;   // wave = v * 2 + side
+    Neumaier a, m;
+    for (int b = lane; b < nb; b += 64) {
+        const double *o = part + ((size_t)wave * nb + b) * 4;
+        a.merge(o[0], o[1]);
+        m.merge(o[2], o[3]);
+    }
+    a = cons_wave_sum(a);
+    m = cons_wave_sum(m);
+    if (lane == 0) {
+        res[wave][0] = a.s + a.c;
+        res[wave][1] = m.s + m.c;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        const int v = threadIdx.x;
+        out[v * 3 + 0] = res[v * 2 + 0][0];
+        out[v * 3 + 1] = res[v * 2 + 1][0];
+        out[v * 3 + 2] = res[v * 2 + 0][1] + res[v * 2 + 1][1];
+    }
 }
 
-// Blocks of the conservation sums: about four (point, face) elements per thread, at
-// most 2048 blocks.
+// Blocks per (variable, side) of the conservation sums: about sixteen (point, face)
+// elements per thread, at most 256.
 int cons_blocks(int P, int nfaces)
 {
     const int64_t total = (int64_t)P * nfaces;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(2048, (total + 1023) / 1024));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(256, (total + 4095) / 4096));
 }
 
 hipError_t launch_conservation(const Iface &f, const void *Fs, const void *Fm, double *d_out,
                                hipStream_t st)
 {
-    const int nblk = cons_blocks(f.P, f.F);
-    const dim3 grid(nblk);
+    const int nb = cons_blocks(f.P, f.F);
+    const dim3 grid(nb, 5, 2);
     if (f.d.precision == MORTAR_FP64)
         hipLaunchKernelGGL(k_cons_partial<double>, grid, dim3(256), 0, st,
                            (const double *)Fs, (const double *)Fm, f.d_fid_s, f.d_fid_m,
@@ -327,7 +330,7 @@ hipError_t launch_conservation(const Iface &f, const void *Fs, const void *Fm, d
         hipLaunchKernelGGL(k_cons_partial<float>, grid, dim3(256), 0, st,
                            (const float *)Fs, (const float *)Fm, f.d_fid_s, f.d_fid_m,
                            f.d_basis, f.NP, f.F, f.d.n_face_static, f.d.n_face_moving, f.d_cons);
-    hipLaunchKernelGGL(k_cons_final, dim3(1), dim3(256), 0, st, f.d_cons, nblk, d_out);
+    hipLaunchKernelGGL(k_cons_final, dim3(1), dim3(640), 0, st, f.d_cons, nb, d_out);
     return hipGetLastError();
 }
 

@@ -20,6 +20,10 @@ hipError_t launch_flux_f64(const FluxArgs<double> &a, int NP, int grid, bool ns,
 int flux_tile_capacity_f32(int NP, bool ns, bool met);
 int flux_tile_capacity_f64(int NP, bool ns, bool met);
 int flux_occupancy_f32(int NP, bool ns, bool met, int riem);
+int flux_wide_occupancy_f32(int NP, bool ns, bool met, int riem);
+int flux_wide_tile_capacity_f32(int NP, bool ns, bool met);
+hipError_t launch_flux_wide_f32(const FluxArgs<float> &a, int NP, int grid, bool ns, bool met,
+                                int riem, hipStream_t st);
 int flux_occupancy_f64(int NP, bool ns, bool met, int riem);
 int flux_mfma_occupancy_f32(int NP, bool ns, bool met, int riem);
 int flux_mfma_occupancy_f64(int NP, bool ns, bool met, int riem);
@@ -309,6 +313,7 @@ static int variant_occupancy(const Iface &f, int variant)
     if (variant == 1)
         return f.elem == 8 ? flux_mfma_occupancy_f64(f.NP, ns, met, riem)
                            : flux_mfma_occupancy_f32(f.NP, ns, met, riem);
+    if (variant == 3) return flux_wide_occupancy_f32(f.NP, ns, met, riem);
     if (f.lp == 1) return flux_rd_occupancy_bf16(f.NP, ns, met, riem);
     if (f.lp == 2) return flux_rd_occupancy_fp16(f.NP, ns, met, riem);
     return f.elem == 8 ? flux_rd_occupancy_f64(f.NP, ns, met, riem) : flux_rd_occupancy_f32(f.NP, ns, met, riem);
@@ -316,8 +321,9 @@ static int variant_occupancy(const Iface &f, int variant)
 
 static bool variant_allowed(const Iface &f, int variant)
 {
-    if (variant < 0 || variant > 2) return false;
+    if (variant < 0 || variant > 3) return false;
     if (f.lp) return variant == 2;
+    if (variant == 3) return f.elem == 4;
     return variant != 2 || rd_addressable(f.d);
 }
 
@@ -387,7 +393,7 @@ static int setup_one(const mortar_iface_desc &d, Iface &f)
     }
     f.n_cons_blocks = cons_blocks(f.P, f.F);
     if (hipMalloc((void **)&f.d_cons_out, sizeof(double) * 15) != hipSuccess) return MORTAR_ERR_OOM;
-    if (hipMalloc((void **)&f.d_cons, sizeof(double) * 30 * (size_t)f.n_cons_blocks) != hipSuccess)
+    if (hipMalloc((void **)&f.d_cons, sizeof(double) * 40 * (size_t)f.n_cons_blocks) != hipSuccess)
         return MORTAR_ERR_OOM;
     return MORTAR_OK;
 }
@@ -825,6 +831,7 @@ static std::vector<int> tile_candidates(int cap)
 static int vmax_tile(const Iface &f, int variant)
 {
     const bool ns = f.d.physics == MORTAR_NAVIER_STOKES, met = f.d_metrics != nullptr;
+    if (variant == 3) return flux_wide_tile_capacity_f32(f.NP, ns, met);
     if (variant != 0) return 15;
     return f.elem == 8 ? flux_tile_capacity_f64(f.NP, ns, met) : flux_tile_capacity_f32(f.NP, ns, met);
 }
@@ -916,7 +923,7 @@ int mortar_autotune(mortar_handle *h, const void *const *U_s, const void *const 
         };
         int best_v = f.flux_variant, best_t = f.tune_tile;
         float best = 1e30f;
-        for (int v = 0; v <= 2; ++v) {
+        for (int v = 0; v <= 3; ++v) {
             if (!variant_allowed(f, v)) continue;
             f.flux_variant = v;
             f.flux_occ = variant_occupancy(f, v);
@@ -995,7 +1002,8 @@ void fill_args(const Iface &f, const void *Us, const void *Um, const void *Gs,
     const double gm1 = f.d.gamma - 1.0;
     const double kfac = ns ? f.d.mu * f.d.gamma / (gm1 * f.d.Pr) : 0.0;
     const int64_t np = f.d.n_par;
-    int cap = f.flux_variant != 0 ? 15
+    int cap = f.flux_variant == 3 ? flux_wide_tile_capacity_f32(f.NP, ns, met)
+            : f.flux_variant != 0 ? 15
             : (f.elem == 8 ? flux_tile_capacity_f64(f.NP, ns, met)
                            : flux_tile_capacity_f32(f.NP, ns, met));
     if (f.tune_tile > 0) cap = std::min(cap, f.tune_tile);
@@ -1061,6 +1069,7 @@ hipError_t launch_flux(const Iface &f, int n_cu, const void *Us, const void *Um,
     FluxArgs<float> a;
     fill_args(f, Us, Um, Gs, Gm, Fs, Fm, a, n_tiles);
     const int grid = grid_of(n_tiles);
+    if (f.flux_variant == 3) return launch_flux_wide_f32(a, f.NP, grid, ns, met, riem, st);
     return f.flux_variant == 1 ? launch_flux_mfma_f32(a, f.NP, grid, ns, met, riem, st)
                                : launch_flux_f32(a, f.NP, grid, ns, met, riem, st);
 }

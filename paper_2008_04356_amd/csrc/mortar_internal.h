@@ -67,7 +67,7 @@ struct Iface {
     double s = 0.0;
     int64_t nmod_built = -1;           // n mod n_par of the current index map
     bool ready = false;
-    double *d_cons = nullptr;          // conservation partials [blocks][30]
+    double *d_cons = nullptr;          // conservation partials [10][blocks][4]
     double *d_cons_out = nullptr;      // conservation sums [5][3] of the last host query
     int n_cons_blocks = 0;
     int flux_occ = 1;                  // resident flux workgroups per CU

@@ -49,7 +49,7 @@ def test_single_interface_every_variant_and_tile(M):
         n, s = O.decompose(disp[0], spec.l_par)
         ref = H.oracle_flux(spec, oins[0], n, s)
         per_variant = {}
-        for variant in (M.KERNEL_VALU, M.KERNEL_MFMA_LDS, M.KERNEL_REGISTER):
+        for variant in (M.KERNEL_VALU, M.KERNEL_MFMA_LDS, M.KERNEL_REGISTER, M.KERNEL_VALU_WIDE):
             for tile in (0, 11, 6, 3):
                 print(f"[autotune] variant={variant} tile={tile}", flush=True)
                 assert M.mortar_set_tuning(op.h, 0, variant, tile, 0) == 0

@@ -20,8 +20,11 @@ def M():
     return mortar
 
 
-def _run_and_compare(M, spec, disps, seed=1, noise=1e-3, rows=None, check_maps=True):
+def _run_and_compare(M, spec, disps, seed=1, noise=1e-3, rows=None, check_maps=True,
+                     variant=None):
     op = M.MortarOperator([spec])
+    if variant is not None:
+        assert M.mortar_set_tuning(op.h, 0, variant, 0, 0) == 0
     inp = W.make_inputs(spec, seed=seed, delta=disps[0], noise=noise)
     din, oin = H.device_inputs(spec, inp), H.oracle_inputs(spec, inp)
     worst = 0.0
@@ -188,13 +191,53 @@ def test_conservation_on_device(M, precision):
         op.close()
 
 
-@pytest.mark.parametrize("precision", [W.FP32, W.FP64])
-def test_benchmark_workload_full_size_sampled_rows(M, precision):
-    """The benchmark's plane N=5, 128x64, NS Roe+BR1 interface at full size, with the
-    benchmark's launch configuration; the oracle checks sampled rows (all rows are
-    computed by the same kernel)."""
+# every launch variant the autotuner may pick: VALU, MFMA-LDS, register-direct, and
+# (FP32 only) wide-tile VALU
+_VARIANTS = {W.FP32: (0, 1, 2, 3), W.FP64: (0, 1, 2)}
+
+
+@pytest.mark.parametrize("precision,variant",
+                         [(p, v) for p in (W.FP32, W.FP64) for v in _VARIANTS[p]])
+def test_benchmark_workload_full_size_sampled_rows(M, precision, variant):
+    """The benchmark's plane N=5, 128x64, NS Roe+BR1 interface at full size, in every
+    launch variant; the oracle checks sampled rows (all rows are computed by the same
+    kernel)."""
     specs, disp = W.config(2, precision=precision)
     spec = specs[0]
     for k in (1, 137):
         _run_and_compare(M, spec, [disp(k)[0]], seed=2, noise=1e-4, rows=(5, 8),
-                         check_maps=(k == 137))
+                         check_maps=(k == 137), variant=variant)
+
+
+@pytest.mark.parametrize("precision,variant",
+                         [(p, v) for p in (W.FP32, W.FP64) for v in _VARIANTS[p]])
+def test_annulus_workload_full_size_sampled_rows(M, precision, variant):
+    """The annular interface N=7, 512x64 with per-point metrics at full size."""
+    specs, disp = W.config(3, precision=precision)
+    spec = specs[0]
+    _run_and_compare(M, spec, [disp(211)[0]], seed=3, noise=1e-4, rows=(31, 33),
+                     check_maps=False, variant=variant)
+
+
+@pytest.mark.parametrize("variant", (0, 2))
+def test_turbine_batch_full_size_sampled_rows(M, variant):
+    """The three-interface turbine-like batch at full size in one persistent launch
+    (VALU or register-direct batch kernel), two sampled rows per interface."""
+    specs, disp = W.config(4, precision=W.FP32)
+    d = disp(57)
+    op = M.MortarOperator(specs)
+    try:
+        assert M.mortar_set_tuning(op.h, 0, variant, 0, 0) == 0
+        inps = [W.make_inputs(s, seed=4 + i, delta=d[i], noise=1e-4) for i, s in enumerate(specs)]
+        dins = [H.device_inputs(s, x) for s, x in zip(specs, inps)]
+        op.update(d)
+        outs = H.gpu_flux(op, specs, dins)
+        for i, s in enumerate(specs):
+            n, sf = O.decompose(d[i], s.l_par)
+            rows = (s.n_perp // 2, s.n_perp // 2 + 2)
+            ref = H.oracle_flux(s, H.oracle_inputs(s, inps[i]), n, sf, rows=rows)
+            err = H.rel_err(s, (outs[i][0].cpu().numpy(), outs[i][1].cpu().numpy()), ref, rows=rows)
+            print(f"[parity] C4 {s.name} variant {variant}: {err}", flush=True)
+            assert np.max(err) <= H.TOL[W.FP32], (s.name, err)
+    finally:
+        op.close()
