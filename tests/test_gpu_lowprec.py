@@ -85,8 +85,9 @@ def test_annulus_metrics_lowprec(M, precision):
     _lowprec_case(M, spec, [0.2 * spec.l_par, 3.7 * spec.l_par])
 
 
-@pytest.mark.parametrize("precision", [W.BF16_MFMA, W.FP16_MFMA])
-def test_c5_full_size_sampled_rows(M, precision):
+@pytest.mark.parametrize("precision,variant", [(W.BF16_MFMA, 2), (W.FP16_MFMA, 2),
+                                               (W.BF16_MFMA, 4), (W.FP16_MFMA, 4)])
+def test_c5_full_size_sampled_rows(M, precision, variant):
     """The precision-stress workload at full size (plane N = 9, 256 x 256; surface
     elements of 3.8e-6 put the fluxes far below fp16's normal range before scaling);
     the oracle checks three rows."""
@@ -95,6 +96,7 @@ def test_c5_full_size_sampled_rows(M, precision):
     d = disp(37)[0]
     op = M.MortarOperator([spec])
     try:
+        assert M.mortar_set_tuning(op.h, 0, variant, 0, 0) == 0
         inp = W.make_inputs(spec, seed=2, delta=d, noise=1e-4)
         din, oin = H.device_inputs(spec, inp), H.oracle_inputs(spec, inp)
         op.update([d])
