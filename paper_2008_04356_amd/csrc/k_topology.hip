@@ -177,10 +177,10 @@ hipError_t launch_index_map(Iface &f, int side, hipStream_t st)
 }
 
 // ------------------------------------------------------------------------------------
-// Conservation sums (FP64, compensated).  Each block sums a fixed set of (point, face)
-// elements of one variable on one side; the threads of a block and then the block
-// partials are combined in fixed orders (xor trees within waves, waves in sequence), so
-// the result is deterministic.  Each accumulator is a Neumaier pair (sum, correction).
+// Conservation sums (FP64).  Each block sums a fixed set of (face, point) elements of
+// one variable on one side with Neumaier compensation per thread; threads, waves and
+// blocks are then combined in fixed orders (xor trees within waves, waves and blocks in
+// sequence), so the result is deterministic.
 // ------------------------------------------------------------------------------------
 
 struct Neumaier {
@@ -198,26 +198,20 @@ struct Neumaier {
     }
 };
 
-// Combination of a wave's Neumaier pairs by a fixed xor tree (both partners form the
-// same sum, lower lane first), so every lane ends with the wave's total.
-__device__ __forceinline__ Neumaier cons_wave_sum(Neumaier x)
+// Plain double sum over a wave by a fixed xor tree (addition is commutative, so both
+// partners of every step form the same value and the result is deterministic).
+__device__ __forceinline__ double cons_wave_add(double x)
 {
 #pragma unroll
-    for (int m = 1; m < 64; m <<= 1) {
-        const double os = __shfl_xor(x.s, m), oc = __shfl_xor(x.c, m);
-        const bool lower = (threadIdx.x & m) == 0;
-        Neumaier t;
-        t.s = lower ? x.s : os;
-        t.c = lower ? x.c : oc;
-        t.merge(lower ? os : x.s, lower ? oc : x.c);
-        x = t;
-    }
+    for (int m = 1; m < 64; m <<= 1) x += __shfl_xor(x, m);
     return x;
 }
 
-// Partial sums: block (b, v, side) sums w_p w_q F and w_p w_q |F| of variable v on one
-// side over the (point, face) elements k = p * nfaces + f, k = b*256 + t + j*nb*256.
-// part[(v * 2 + side) * nb + b][2 pairs][2].
+// Partial sums: block (bx, by, g) with g = v * 2 + side sums w_p w_q F and w_p w_q |F|
+// of variable v on one side over the faces f = bx*256 + t + j*gridDim.x*256 and the
+// points p = 8 by .. 8 by + 7 (consecutive threads read consecutive face columns).
+// Each thread accumulates with compensation; the few levels that combine threads and
+// blocks add plain doubles in fixed orders.  part[(g * gridDim.y + by) * gridDim.x + bx][2].
 template <typename T>
 __global__ __launch_bounds__(256) void k_cons_partial(const T *__restrict__ Fs,
                                                       const T *__restrict__ Fm,
@@ -227,101 +221,94 @@ __global__ __launch_bounds__(256) void k_cons_partial(const T *__restrict__ Fs,
                                                       int NP, int nfaces, int nfs, int nfm,
                                                       double *__restrict__ part)
 {
-    __shared__ double wq[kMaxNP * kMaxNP];
-    __shared__ double red[4][2][2];
+    constexpr int PG = 8;
+    __shared__ double red[4][2];
     const int P = NP * NP;
-    for (int p = threadIdx.x; p < P; p += blockDim.x) wq[p] = basis->w[p % NP] * basis->w[p / NP];
-    __syncthreads();
-    const int v = blockIdx.y, side = blockIdx.z;
-    const T *F = (side ? Fm : Fs) + (size_t)v * P * (side ? nfm : nfs);
-    const int32_t *fid = side ? fid_m : fid_s;
+    const int g = blockIdx.z, v = g >> 1, side = g & 1;
     const int nf = side ? nfm : nfs;
+    const T *F = (side ? Fm : Fs) + (size_t)v * P * nf;
+    const int32_t *fid = side ? fid_m : fid_s;
+    const int p0 = PG * blockIdx.y;
+    double w[PG];
+#pragma unroll
+    for (int u = 0; u < PG; ++u) {
+        const int p = p0 + u;
+        w[u] = p < P ? basis->w[p % NP] * basis->w[p / NP] : 0.0;
+    }
     Neumaier sum, mag;
-    const int64_t total = (int64_t)P * nfaces;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t k0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k0 < total; k0 += 4 * stride) {
-        T x[4];
-        double w[4];
+    for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < nfaces; f += gridDim.x * blockDim.x) {
+        const T *col = F + fid[f];
+        T x[PG];
+        // unconditional loads (a point past P rereads the last one, with weight 0), so
+        // all of them are in flight at once
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {       // the four loads are issued before the adds
-            const int64_t k = k0 + u * stride;
-            const bool ok = k < total;
-            const int p = ok ? (int)(k / nfaces) : 0, f = ok ? (int)(k - (int64_t)p * nfaces) : 0;
-            w[u] = ok ? wq[p] : 0.0;
-            x[u] = F[(size_t)p * nf + fid[f]];
-        }
+        for (int u = 0; u < PG; ++u) x[u] = col[(size_t)min(p0 + u, P - 1) * nf];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < PG; ++u) {
             const double y = w[u] * (double)x[u];
             sum.add(y);
             mag.add(fabs(y));
         }
     }
-    sum = cons_wave_sum(sum);
-    mag = cons_wave_sum(mag);
+    const double s1 = cons_wave_add(sum.s + sum.c), s2 = cons_wave_add(mag.s + mag.c);
     const int wave = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
-        red[wave][0][0] = sum.s;
-        red[wave][0][1] = sum.c;
-        red[wave][1][0] = mag.s;
-        red[wave][1][1] = mag.c;
+        red[wave][0] = s1;
+        red[wave][1] = s2;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        Neumaier a, m;
+        double a = 0.0, m = 0.0;
         for (int w2 = 0; w2 < (int)(blockDim.x >> 6); ++w2) {
-            a.merge(red[w2][0][0], red[w2][0][1]);
-            m.merge(red[w2][1][0], red[w2][1][1]);
+            a += red[w2][0];
+            m += red[w2][1];
         }
-        double *o = part + (((size_t)v * 2 + side) * gridDim.x + blockIdx.x) * 4;
-        o[0] = a.s;
-        o[1] = a.c;
-        o[2] = m.s;
-        o[3] = m.c;
+        double *o = part + (((size_t)g * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * 2;
+        o[0] = a;
+        o[1] = m;
     }
 }
 
-// Final pass: wave (v, side) adds its nb partials in a fixed order (xor tree); then
-// out[v][0] = static integral, out[v][1] = moving integral, out[v][2] = sum of |terms|.
+// Final pass: wave g = v * 2 + side adds its group's partials in a fixed order
+// (compensated lane-stride sums, then the xor tree); out[v][0] = static integral,
+// out[v][1] = moving integral, out[v][2] = sum of |terms|.
 __global__ __launch_bounds__(640) void k_cons_final(const double *__restrict__ part, int nb,
                                                     double *__restrict__ out)
 {
     __shared__ double res[10][2];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;   // wave = v * 2 + side
+    const int g = threadIdx.x >> 6, lane = threadIdx.x & 63;
     Neumaier a, m;
     for (int b = lane; b < nb; b += 64) {
-        const double *o = part + ((size_t)wave * nb + b) * 4;
-        a.merge(o[0], o[1]);
-        m.merge(o[2], o[3]);
+        a.add(part[((size_t)g * nb + b) * 2 + 0]);
+        m.add(part[((size_t)g * nb + b) * 2 + 1]);
     }
-    a = cons_wave_sum(a);
-    m = cons_wave_sum(m);
+    const double sa = cons_wave_add(a.s + a.c), sm = cons_wave_add(m.s + m.c);
     if (lane == 0) {
-        res[wave][0] = a.s + a.c;
-        res[wave][1] = m.s + m.c;
+        res[g][0] = sa;
+        res[g][1] = sm;
     }
     __syncthreads();
     if (threadIdx.x < 5) {
-        const int v = threadIdx.x;
-        out[v * 3 + 0] = res[v * 2 + 0][0];
-        out[v * 3 + 1] = res[v * 2 + 1][0];
-        out[v * 3 + 2] = res[v * 2 + 0][1] + res[v * 2 + 1][1];
+        const int vv = threadIdx.x;
+        out[vv * 3 + 0] = res[vv * 2 + 0][0];
+        out[vv * 3 + 1] = res[vv * 2 + 1][0];
+        out[vv * 3 + 2] = res[vv * 2 + 0][1] + res[vv * 2 + 1][1];
     }
 }
 
-// Blocks per (variable, side) of the conservation sums: about sixteen (point, face)
-// elements per thread, at most 256.
-int cons_blocks(int P, int nfaces)
-{
-    const int64_t total = (int64_t)P * nfaces;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(256, (total + 4095) / 4096));
-}
+// Conservation grid: blocks along the faces (one face per thread, at most 256 blocks;
+// larger interfaces loop) and point groups of eight.  The pass is latency-bound (face
+// column, then its values), so one face per thread keeps the chain short.
+static int cons_face_blocks(int nfaces) { return std::max(1, std::min(256, (nfaces + 255) / 256)); }
+
+// Partials per (variable, side) group.
+int cons_blocks(int P, int nfaces) { return cons_face_blocks(nfaces) * ((P + 7) / 8); }
 
 hipError_t launch_conservation(const Iface &f, const void *Fs, const void *Fm, double *d_out,
                                hipStream_t st)
 {
-    const int nb = cons_blocks(f.P, f.F);
-    const dim3 grid(nb, 5, 2);
+    const dim3 grid(cons_face_blocks(f.F), (f.P + 7) / 8, 10);
+    const int nb = (int)(grid.x * grid.y);
     if (f.d.precision == MORTAR_FP64)
         hipLaunchKernelGGL(k_cons_partial<double>, grid, dim3(256), 0, st,
                            (const double *)Fs, (const double *)Fm, f.d_fid_s, f.d_fid_m,
