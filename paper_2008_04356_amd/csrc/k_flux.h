@@ -128,6 +128,7 @@ struct FluxCfg {
     static constexpr int NIT_M = V * (TF + 1);
     static constexpr int ITEMS = ((NIT_S > NIT_M ? NIT_S : NIT_M) + kHalf - 1) / kHalf;
     static constexpr int ROUNDS = ((2 * TF + 1) * NP + kFluxThreads - 1) / kFluxThreads;
+    static constexpr int ITEMS3 = (10 * TF + kFluxThreads - 1) / kFluxThreads;  // back projection
     static constexpr int LDS_T = (VS + V) * NP * LD;    // state region (elements of T)
 };
 
@@ -148,41 +149,92 @@ __device__ __forceinline__ TileGeom tile_geom(const FluxArgs<T> &a, int t, int N
     return g;
 }
 
-// Phase 0: issue the global loads of every face line this thread projects.
+// Phase 0, in two steps: the face columns of the items this thread projects (loaded one
+// phase ahead), then the loads of their face lines.  Vector-memory operations complete
+// in issue order, so waiting for a column that was loaded long before costs nothing,
+// while a column loaded right before its use would also wait for every store and load
+// issued before it.
 template <typename C, typename T, int NP>
-__device__ __forceinline__ void prefetch(const FluxArgs<T> &a, const TileGeom &g, int side, int lt,
-                                         T (&u)[C::ITEMS][NP])
+__device__ __forceinline__ void prefetch_cols(const FluxArgs<T> &a, const TileGeom &g, int side,
+                                              int lt, int (&cols)[C::ITEMS])
 {
-    constexpr int V = C::V, TF = C::TF;
+    constexpr int TF = C::TF;
     const int np_ = a.n_par;
-    const size_t plane_s = (size_t)NP * NP * a.nfs, plane_m = (size_t)NP * NP * a.nfm;
     const int nit = side ? C::NIT_M : C::NIT_S;
 #pragma unroll
     for (int k = 0; k < C::ITEMS; ++k) {
         const int it = lt + k * kHalf;
         const int v = it / (TF + 1);
         const int f = it - v * (TF + 1);
-        const bool ok = it < nit && f <= g.nf;
-        const T *src = nullptr;
-        size_t stride = 0;
-        if (ok) {
+        cols[k] = -1;
+        if (it < nit && f <= g.nf) {
             if (!side) {                    // static slot f: face i0 - 1 + f (slot 0 = halo)
                 int i = g.i0 - 1 + f;
                 if (i < 0) i += np_;
-                const int col = a.fid_s[(size_t)g.row * np_ + i];
-                src = (v < 5 ? a.Us + v * plane_s
-                             : (v < V ? a.Gs + (v - 5) * plane_s : a.met + (v - V) * plane_s)) + col;
-                stride = a.nfs;
+                cols[k] = a.fid_s[(size_t)g.row * np_ + i];
             } else {                        // moving slot f: face i0 + f - n - 1
                 int jt = g.i0 + f - a.nmod - 1;
                 if (jt < 0) jt += np_;
-                const int col = a.fid_m[(size_t)g.row * np_ + jt];
-                src = (v < 5 ? a.Um + v * plane_m : a.Gm + (v - 5) * plane_m) + col;
+                cols[k] = a.fid_m[(size_t)g.row * np_ + jt];
+            }
+        }
+    }
+}
+
+template <typename C, typename T, int NP>
+__device__ __forceinline__ void prefetch(const FluxArgs<T> &a, const TileGeom &g, int side, int lt,
+                                         const int (&cols)[C::ITEMS], T (&u)[C::ITEMS][NP])
+{
+    constexpr int V = C::V, TF = C::TF;
+    const size_t plane_s = (size_t)NP * NP * a.nfs, plane_m = (size_t)NP * NP * a.nfm;
+#pragma unroll
+    for (int k = 0; k < C::ITEMS; ++k) {
+        const int it = lt + k * kHalf;
+        const int v = it / (TF + 1);
+        const bool ok = cols[k] >= 0;
+        const T *src = nullptr;
+        size_t stride = 0;
+        if (ok) {
+            if (!side) {
+                src = (v < 5 ? a.Us + v * plane_s
+                             : (v < V ? a.Gs + (v - 5) * plane_s : a.met + (v - V) * plane_s)) + cols[k];
+                stride = a.nfs;
+            } else {
+                src = (v < 5 ? a.Um + v * plane_m : a.Gm + (v - 5) * plane_m) + cols[k];
                 stride = a.nfm;
             }
         }
 #pragma unroll
         for (int j = 0; j < NP; ++j) u[k][j] = ok ? src[(size_t)(j + NP * g.pp) * stride] : T(0);
+    }
+}
+
+// Output face columns of the back-projection items of this thread (item it = tid + k*256:
+// side, variable, face f of the tile), -1 where the item does not exist.
+template <typename C, typename T>
+__device__ __forceinline__ void out_cols(const FluxArgs<T> &a, const TileGeom &g, int tid,
+                                         int (&col3)[C::ITEMS3])
+{
+    constexpr int TF = C::TF;
+    const int np_ = a.n_par;
+#pragma unroll
+    for (int k = 0; k < C::ITEMS3; ++k) {
+        const int it = tid + k * kFluxThreads;
+        col3[k] = -1;
+        if (it < 10 * TF) {
+            const int sd = it >= 5 * TF;
+            const int e = sd ? it - 5 * TF : it;
+            const int f = e - (e / TF) * TF;
+            if (f < g.nf) {
+                if (sd) {
+                    int jt = g.i0 + f - a.nmod - 1;
+                    if (jt < 0) jt += np_;
+                    col3[k] = a.fid_m[(size_t)g.row * np_ + jt];
+                } else {
+                    col3[k] = a.fid_s[(size_t)g.row * np_ + g.i0 + f];
+                }
+            }
+        }
     }
 }
 
@@ -219,13 +271,24 @@ __device__ __forceinline__ void run_interface(const FluxArgs<T> &a, TileCursor &
 
     TileGeom g = tile_geom(a, cur.tile(), NP);
     T u[C::ITEMS][NP];
-    prefetch<C, T, NP>(a, g, side, lt, u);
+    int cols[C::ITEMS], col3[C::ITEMS3];
+    prefetch_cols<C, T, NP>(a, g, side, lt, cols);
+    prefetch<C, T, NP>(a, g, side, lt, cols, u);
 
     // FP64 matrices for this stage, once per workgroup and interface
     assemble_matrices<NP, T>(a.basis, a.s, reinterpret_cast<double *>(lds), nullptr, nullptr,
                              mats, mats + 4 * NN);
 
     while (true) {
+        // this tile's output columns and the next tile's input columns, early
+        out_cols<C, T>(a, g, tid, col3);
+        cur.next();
+        const bool more = cur.valid();
+        TileGeom gn = g;
+        if (more) {
+            gn = tile_geom(a, cur.tile(), NP);
+            prefetch_cols<C, T, NP>(a, gn, side, lt, cols);
+        }
         // ---- phase 1: forward projection (register mat-vec) ------------------------
         {
             // static: Pf0 -> slot 2f-1 (column 2f), Pf1 -> slot 2f (column 2f+1)
@@ -256,13 +319,7 @@ __device__ __forceinline__ void run_interface(const FluxArgs<T> &a, TileCursor &
             }
         }
         // the next tile's loads fly while this tile's flux and back projection run
-        cur.next();
-        const bool more = cur.valid();
-        TileGeom gn = g;
-        if (more) {
-            gn = tile_geom(a, cur.tile(), NP);
-            prefetch<C, T, NP>(a, gn, side, lt, u);
-        }
+        if (more) prefetch<C, T, NP>(a, gn, side, lt, cols, u);
         __syncthreads();
 
         // ---- phase 2: flux at every mortar node -------------------------------------
@@ -320,14 +377,14 @@ __device__ __forceinline__ void run_interface(const FluxArgs<T> &a, TileCursor &
 
         // ---- phase 3: back projection onto both sides -------------------------------
         const T *Pb = mats + 4 * NN;
-        const int32_t *fs_row = a.fid_s + (size_t)g.row * np_;
-        const int32_t *fm_row = a.fid_m + (size_t)g.row * np_;
-        for (int it = tid; it < 10 * TF; it += kFluxThreads) {
+#pragma unroll
+        for (int k3 = 0; k3 < C::ITEMS3; ++k3) {
+            const int it = tid + k3 * kFluxThreads;
+            if (col3[k3] < 0) continue;
             const int sd = it >= 5 * TF;
             const int e = sd ? it - 5 * TF : it;
             const int v = e / TF;
             const int f = e - v * TF;
-            if (f >= g.nf) continue;
             const T *src = ldsF + v * NP * LD;
             // static face i0+f: mortars (i0+f, 0) slot 2f+1 and (i0+f, 1) slot 2f+2
             // moving face i0+f-n-1: lower (i0+f-1, 1) slot 2f, upper (i0+f, 0) slot 2f+1
@@ -343,12 +400,10 @@ __device__ __forceinline__ void run_interface(const FluxArgs<T> &a, TileCursor &
             T *dst;
             size_t stride;
             if (sd) {
-                int jt = g.i0 + f - nmod - 1;
-                if (jt < 0) jt += np_;
-                dst = a.Fm + v * plane_m + fm_row[jt];
+                dst = a.Fm + v * plane_m + col3[k3];
                 stride = a.nfm;
             } else {
-                dst = a.Fs + v * plane_s + fs_row[g.i0 + f];
+                dst = a.Fs + v * plane_s + col3[k3];
                 stride = a.nfs;
             }
 #pragma unroll
