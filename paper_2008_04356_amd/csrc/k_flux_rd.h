@@ -215,7 +215,7 @@ struct WaveCursor {
 // One interface: every workgroup assembles the stage's matrices, then its waves take
 // tiles from the interface's wave cursor.  work: LDS of 8 NP^2 doubles; mats: 8 NP^2
 // element-type values; wq: NP doubles.  Contains __syncthreads (all threads call it).
-template <typename T, int NP, bool NSV, bool MET, int RIEM, int PREC, bool PF>
+template <typename T, int NP, bool NSV, bool MET, int RIEM, int PREC>
 __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work, T *mats, double *wq)
 {
     using Op = RdOp<T, PREC>;
@@ -355,8 +355,8 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
         if (jt < 0) jt += np_;
         return col <= g.nf ? a.fid_m[(size_t)g.row * np_ + jt] : 0;
     };
-    auto fetch_s = [&](const TileGeom &g) {
-        const uint32_t cs = (uint32_t)col_s(g), line = (uint32_t)(NP * g.pp);
+    auto fetch_s = [&](const TileGeom &g, int cs_) {
+        const uint32_t cs = (uint32_t)cs_, line = (uint32_t)(NP * g.pp);
         uint32_t os[LF];
 #pragma unroll
         for (int ks = 0; ks < KSF; ++ks)
@@ -373,8 +373,8 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
             for (int q = 0; q < LF; ++q) ls[v][q] = rd_load<T>(rs, os[q], pv * pbytes_s);
         }
     };
-    auto fetch_m = [&](const TileGeom &g) {
-        const uint32_t cm = (uint32_t)col_m(g), line = (uint32_t)(NP * g.pp);
+    auto fetch_m = [&](const TileGeom &g, int cm_) {
+        const uint32_t cm = (uint32_t)cm_, line = (uint32_t)(NP * g.pp);
         uint32_t om[LM];
 #pragma unroll
         for (int ks = 0; ks < KSM; ++ks)
@@ -468,22 +468,24 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
     // lane's mortar nodes are evaluated one after the other: an empty asm statement that
     // takes the previous node's flux and redefines the next node's inputs stops the
     // compiler from interleaving all of them (which multiplies the live temporaries).
-    // PF (prefetch): the next tile's loads go into ls / lm as soon as this tile's last
-    // projection from them is made, and fly while this tile's fluxes, back projection
-    // and stores run (more registers: fewer waves per SIMD).  Without PF a tile's loads
-    // are issued at its start and the other waves of the SIMD cover their latency.
+    // A tile's loads are issued at its start and the other waves of the SIMD cover their
+    // latency.  The face columns of the next tile are looked up at the start of the
+    // current one: vector-memory operations complete in issue order, so a column loaded
+    // right before the loads that need it would also wait for the previous tile's stores.
     WaveCursor cur(a.n_tiles, C::WAVES, wave);
     bool more = cur.valid();
     TileGeom g = tile_geom(a, more ? cur.tile() : 0, NP);
-    if (PF && more) {
-        fetch_s(g);
-        fetch_m(g);
-    }
+    int cs_n = more ? col_s(g) : 0, cm_n = more ? col_m(g) : 0;
     while (more) {
         const TileGeom gc = g;
-        if constexpr (!PF) {
-            fetch_s(gc);
-            fetch_m(gc);
+        fetch_s(gc, cs_n);
+        fetch_m(gc, cm_n);
+        cur.next();
+        more = cur.valid();
+        if (more) {
+            g = tile_geom(a, cur.tile(), NP);
+            cs_n = col_s(g);
+            cm_n = col_m(g);
         }
         acc_t QL[5][RB], QR[5][RB], MT[MET ? 4 : 1][RB];
 #pragma unroll
@@ -495,15 +497,7 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
 #pragma unroll
             for (int c = 0; c < 4; ++c) proj_s(ls[V + c], MT[c]);
         }
-        cur.next();
-        more = cur.valid();
-        if (more) g = tile_geom(a, cur.tile(), NP);
-        if constexpr (PF && !NSV) {
-            if (more) {
-                fetch_s(g);
-                fetch_m(g);
-            }
-        }
+
         // rows of this lane that are mortar nodes the tile needs: mortar (i0-1+col, 0)
         // for col >= 1, mortar (i0-1+col, 1) for every live column
         const bool live = col <= gc.nf;
@@ -561,10 +555,7 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
                     if (sd == 0) proj_s(ls[5 + gg], GQ[gg]);
                     else proj_m(lm[5 + gg], GQ[gg]);
                 }
-                if (PF && more) {
-                    if (sd == 0) fetch_s(g);
-                    else fetch_m(g);
-                }
+
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
@@ -704,13 +695,13 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
     }
 }
 
-template <typename T, int NP, bool NSV, bool MET, int RIEM, int PREC, bool PF>
+template <typename T, int NP, bool NSV, bool MET, int RIEM, int PREC>
 __global__ __launch_bounds__(256) void k_mortar_flux_rd(FluxArgs<T> a)
 {
     __shared__ double work[8 * NP * NP];
     __shared__ T mats[8 * NP * NP];          // Pf[4][NP][NP], Pb[4][NP][NP]
     __shared__ double wq[NP];
-    rd_interface<T, NP, NSV, MET, RIEM, PREC, PF>(a, work, mats, wq);
+    rd_interface<T, NP, NSV, MET, RIEM, PREC>(a, work, mats, wq);
 }
 
 // Every interface of a batch in one persistent launch (degrees N = 3, 5, 7, element type
@@ -728,8 +719,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         const bool met = b.met[i] != 0;
 #define MORTAR_RD_BATCH_NP(NPV)                                                               \
     if (b.np[i] == NPV) {                                                                     \
-        if (met) rd_interface<float, NPV, NSV, true, RIEM, 0, false>(b.a[i], work, mats, wq);        \
-        else rd_interface<float, NPV, NSV, false, RIEM, 0, false>(b.a[i], work, mats, wq);           \
+        if (met) rd_interface<float, NPV, NSV, true, RIEM, 0>(b.a[i], work, mats, wq);        \
+        else rd_interface<float, NPV, NSV, false, RIEM, 0>(b.a[i], work, mats, wq);           \
         continue;                                                                             \
     }
         MORTAR_RD_BATCH_NP(4) MORTAR_RD_BATCH_NP(6) MORTAR_RD_BATCH_NP(8)
@@ -742,51 +733,51 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // ---- launch helpers shared by the instantiation units --------------------------------
 namespace mortar {
 
-template <typename T, int NP, bool NSV, bool MET, int RIEM, int PREC, bool PF>
+template <typename T, int NP, bool NSV, bool MET, int RIEM, int PREC>
 static hipError_t rd_go(const FluxArgs<T> &a, int grid, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_mortar_flux_rd<T, NP, NSV, MET, RIEM, PREC, PF>), dim3(grid), dim3(256), 0,
+    hipLaunchKernelGGL((k_mortar_flux_rd<T, NP, NSV, MET, RIEM, PREC>), dim3(grid), dim3(256), 0,
                        st, a);
     return hipGetLastError();
 }
 
-template <typename T, int NP, bool NSV, bool MET, int RIEM, int PREC, bool PF>
+template <typename T, int NP, bool NSV, bool MET, int RIEM, int PREC>
 static int rd_occ1()
 {
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &nb, reinterpret_cast<const void *>(&k_mortar_flux_rd<T, NP, NSV, MET, RIEM, PREC, PF>), 256,
+            &nb, reinterpret_cast<const void *>(&k_mortar_flux_rd<T, NP, NSV, MET, RIEM, PREC>), 256,
             0) != hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }
 
 // Dispatch over (physics, metrics, Riemann solver) for one degree and precision mode.
-template <typename T, int NP, int PREC, bool PF>
+template <typename T, int NP, int PREC>
 static hipError_t rd_pick(const FluxArgs<T> &a, int grid, bool ns, bool met, int riem,
                           hipStream_t st)
 {
     if (ns) {
-        if (met) return riem ? rd_go<T, NP, true, true, 1, PREC, PF>(a, grid, st)
-                             : rd_go<T, NP, true, true, 0, PREC, PF>(a, grid, st);
-        return riem ? rd_go<T, NP, true, false, 1, PREC, PF>(a, grid, st)
-                    : rd_go<T, NP, true, false, 0, PREC, PF>(a, grid, st);
+        if (met) return riem ? rd_go<T, NP, true, true, 1, PREC>(a, grid, st)
+                             : rd_go<T, NP, true, true, 0, PREC>(a, grid, st);
+        return riem ? rd_go<T, NP, true, false, 1, PREC>(a, grid, st)
+                    : rd_go<T, NP, true, false, 0, PREC>(a, grid, st);
     }
-    if (met) return riem ? rd_go<T, NP, false, true, 1, PREC, PF>(a, grid, st)
-                         : rd_go<T, NP, false, true, 0, PREC, PF>(a, grid, st);
-    return riem ? rd_go<T, NP, false, false, 1, PREC, PF>(a, grid, st)
-                : rd_go<T, NP, false, false, 0, PREC, PF>(a, grid, st);
+    if (met) return riem ? rd_go<T, NP, false, true, 1, PREC>(a, grid, st)
+                         : rd_go<T, NP, false, true, 0, PREC>(a, grid, st);
+    return riem ? rd_go<T, NP, false, false, 1, PREC>(a, grid, st)
+                : rd_go<T, NP, false, false, 0, PREC>(a, grid, st);
 }
 
-template <typename T, int NP, int PREC, bool PF>
+template <typename T, int NP, int PREC>
 static int rd_occ(bool ns, bool met, int riem)
 {
     if (ns) {
-        if (met) return riem ? rd_occ1<T, NP, true, true, 1, PREC, PF>() : rd_occ1<T, NP, true, true, 0, PREC, PF>();
-        return riem ? rd_occ1<T, NP, true, false, 1, PREC, PF>() : rd_occ1<T, NP, true, false, 0, PREC, PF>();
+        if (met) return riem ? rd_occ1<T, NP, true, true, 1, PREC>() : rd_occ1<T, NP, true, true, 0, PREC>();
+        return riem ? rd_occ1<T, NP, true, false, 1, PREC>() : rd_occ1<T, NP, true, false, 0, PREC>();
     }
-    if (met) return riem ? rd_occ1<T, NP, false, true, 1, PREC, PF>() : rd_occ1<T, NP, false, true, 0, PREC, PF>();
-    return riem ? rd_occ1<T, NP, false, false, 1, PREC, PF>() : rd_occ1<T, NP, false, false, 0, PREC, PF>();
+    if (met) return riem ? rd_occ1<T, NP, false, true, 1, PREC>() : rd_occ1<T, NP, false, true, 0, PREC>();
+    return riem ? rd_occ1<T, NP, false, false, 1, PREC>() : rd_occ1<T, NP, false, false, 0, PREC>();
 }
 
 }  // namespace mortar

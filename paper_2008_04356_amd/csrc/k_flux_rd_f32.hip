@@ -5,7 +5,7 @@ namespace mortar {
 
 int flux_rd_occupancy_f32(int NP, bool ns, bool met, int riem)
 {
-#define E(np) rd_occ<float, np, 0, false>(ns, met, riem)
+#define E(np) rd_occ<float, np, 0>(ns, met, riem)
     MORTAR_RD_NP_SWITCH(E, 1)
 #undef E
 }
@@ -13,7 +13,7 @@ int flux_rd_occupancy_f32(int NP, bool ns, bool met, int riem)
 hipError_t launch_flux_rd_f32(const FluxArgs<float> &a, int NP, int grid, bool ns, bool met,
                               int riem, hipStream_t st)
 {
-#define E(np) rd_pick<float, np, 0, false>(a, grid, ns, met, riem, st)
+#define E(np) rd_pick<float, np, 0>(a, grid, ns, met, riem, st)
     MORTAR_RD_NP_SWITCH(E, hipErrorInvalidValue)
 #undef E
 }

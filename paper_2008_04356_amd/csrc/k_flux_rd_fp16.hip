@@ -6,7 +6,7 @@ namespace mortar {
 
 int flux_rd_occupancy_fp16(int NP, bool ns, bool met, int riem)
 {
-#define E(np) rd_occ<float, np, 2, false>(ns, met, riem)
+#define E(np) rd_occ<float, np, 2>(ns, met, riem)
     MORTAR_RD_NP_SWITCH(E, 1)
 #undef E
 }
@@ -14,7 +14,7 @@ int flux_rd_occupancy_fp16(int NP, bool ns, bool met, int riem)
 hipError_t launch_flux_rd_fp16(const FluxArgs<float> &a, int NP, int grid, bool ns, bool met,
                                int riem, hipStream_t st)
 {
-#define E(np) rd_pick<float, np, 2, false>(a, grid, ns, met, riem, st)
+#define E(np) rd_pick<float, np, 2>(a, grid, ns, met, riem, st)
     MORTAR_RD_NP_SWITCH(E, hipErrorInvalidValue)
 #undef E
 }

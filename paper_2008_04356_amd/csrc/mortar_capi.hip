@@ -42,15 +42,7 @@ hipError_t launch_flux_rd_batch_f32(const BatchArgs<float> &b, int grid, bool ns
 int flux_rd_occupancy_f32(int NP, bool ns, bool met, int riem);
 int flux_rd_occupancy_f64(int NP, bool ns, bool met, int riem);
 int flux_rd_occupancy_bf16(int NP, bool ns, bool met, int riem);
-int flux_rd_pf_occupancy_f32(int NP, bool ns, bool met, int riem);
-int flux_rd_pf_occupancy_bf16(int NP, bool ns, bool met, int riem);
-int flux_rd_pf_occupancy_fp16(int NP, bool ns, bool met, int riem);
-hipError_t launch_flux_rd_pf_f32(const FluxArgs<float> &a, int NP, int grid, bool ns, bool met,
-                                 int riem, hipStream_t st);
-hipError_t launch_flux_rd_pf_bf16(const FluxArgs<float> &a, int NP, int grid, bool ns, bool met,
-                                  int riem, hipStream_t st);
-hipError_t launch_flux_rd_pf_fp16(const FluxArgs<float> &a, int NP, int grid, bool ns, bool met,
-                                  int riem, hipStream_t st);
+
 int flux_rd_occupancy_fp16(int NP, bool ns, bool met, int riem);
 hipError_t launch_flux_rd_f32(const FluxArgs<float> &a, int NP, int grid, bool ns, bool met,
                               int riem, hipStream_t st);
@@ -323,11 +315,6 @@ static int variant_occupancy(const Iface &f, int variant)
         return f.elem == 8 ? flux_mfma_occupancy_f64(f.NP, ns, met, riem)
                            : flux_mfma_occupancy_f32(f.NP, ns, met, riem);
     if (variant == 3) return flux_wide_occupancy_f32(f.NP, ns, met, riem);
-    if (variant == 4) {
-        if (f.lp == 1) return flux_rd_pf_occupancy_bf16(f.NP, ns, met, riem);
-        if (f.lp == 2) return flux_rd_pf_occupancy_fp16(f.NP, ns, met, riem);
-        return flux_rd_pf_occupancy_f32(f.NP, ns, met, riem);
-    }
     if (f.lp == 1) return flux_rd_occupancy_bf16(f.NP, ns, met, riem);
     if (f.lp == 2) return flux_rd_occupancy_fp16(f.NP, ns, met, riem);
     return f.elem == 8 ? flux_rd_occupancy_f64(f.NP, ns, met, riem) : flux_rd_occupancy_f32(f.NP, ns, met, riem);
@@ -335,10 +322,9 @@ static int variant_occupancy(const Iface &f, int variant)
 
 static bool variant_allowed(const Iface &f, int variant)
 {
-    if (variant < 0 || variant > 4) return false;
-    if (f.lp) return variant == 2 || variant == 4;
+    if (variant < 0 || variant > 3) return false;
+    if (f.lp) return variant == 2;
     if (variant == 3) return f.elem == 4;
-    if (variant == 4) return f.elem == 4 && rd_addressable(f.d);
     return variant != 2 || rd_addressable(f.d);
 }
 
@@ -938,7 +924,7 @@ int mortar_autotune(mortar_handle *h, const void *const *U_s, const void *const 
         };
         int best_v = f.flux_variant, best_t = f.tune_tile;
         float best = 1e30f;
-        for (int v = 0; v <= 4; ++v) {
+        for (int v = 0; v <= 3; ++v) {
             if (!variant_allowed(f, v)) continue;
             f.flux_variant = v;
             f.flux_occ = variant_occupancy(f, v);
@@ -1051,7 +1037,7 @@ hipError_t launch_flux(const Iface &f, int n_cu, const void *Us, const void *Um,
     const bool met = f.d_metrics != nullptr;
     const int riem = f.d.riemann == MORTAR_FLUX_ROE ? 1 : 0;
     int n_tiles = 0;
-    if (f.flux_variant == 2 || f.flux_variant == 4) {
+    if (f.flux_variant == 2) {
         // one tile per wave, four waves per workgroup; at least one workgroup per XCD
         auto rd_grid = [&](int nt) {
             if (f.tune_grid > 0) return std::max(8, f.tune_grid);
@@ -1065,11 +1051,6 @@ hipError_t launch_flux(const Iface &f, int n_cu, const void *Us, const void *Um,
         FluxArgs<float> a;
         fill_args(f, Us, Um, Gs, Gm, Fs, Fm, a, n_tiles);
         const int grid = rd_grid(n_tiles);
-        if (f.flux_variant == 4) {
-            if (f.lp == 1) return launch_flux_rd_pf_bf16(a, f.NP, grid, ns, met, riem, st);
-            if (f.lp == 2) return launch_flux_rd_pf_fp16(a, f.NP, grid, ns, met, riem, st);
-            return launch_flux_rd_pf_f32(a, f.NP, grid, ns, met, riem, st);
-        }
         if (f.lp == 1) return launch_flux_rd_bf16(a, f.NP, grid, ns, met, riem, st);
         if (f.lp == 2) return launch_flux_rd_fp16(a, f.NP, grid, ns, met, riem, st);
         return launch_flux_rd_f32(a, f.NP, grid, ns, met, riem, st);

@@ -85,8 +85,7 @@ def test_annulus_metrics_lowprec(M, precision):
     _lowprec_case(M, spec, [0.2 * spec.l_par, 3.7 * spec.l_par])
 
 
-@pytest.mark.parametrize("precision,variant", [(W.BF16_MFMA, 2), (W.FP16_MFMA, 2),
-                                               (W.BF16_MFMA, 4), (W.FP16_MFMA, 4)])
+@pytest.mark.parametrize("precision,variant", [(W.BF16_MFMA, 2), (W.FP16_MFMA, 2)])
 def test_c5_full_size_sampled_rows(M, precision, variant):
     """The precision-stress workload at full size (plane N = 9, 256 x 256; surface
     elements of 3.8e-6 put the fluxes far below fp16's normal range before scaling);

@@ -192,8 +192,8 @@ def test_conservation_on_device(M, precision):
 
 
 # every launch variant the autotuner may pick: VALU, MFMA-LDS, register-direct, and
-# (FP32 only) wide-tile VALU and prefetching register-direct
-_VARIANTS = {W.FP32: (0, 1, 2, 3, 4), W.FP64: (0, 1, 2)}
+# (FP32 only) wide-tile VALU
+_VARIANTS = {W.FP32: (0, 1, 2, 3), W.FP64: (0, 1, 2)}
 
 
 @pytest.mark.parametrize("precision,variant",
