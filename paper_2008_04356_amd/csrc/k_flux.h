@@ -34,6 +34,38 @@
 
 namespace mortar {
 
+// Buffer access (bit patterns, no conversion) with a 32-bit per-lane byte offset and a
+// scalar byte offset.  Word 3 of the descriptor: 32-bit data format, no swizzle, raw
+// addressing; an access whose per-lane offset is at or beyond num_records bytes reads 0
+// and writes nothing, which masks lanes without a branch.
+typedef __amdgpu_buffer_rsrc_t buf_rsrc_t;
+__device__ __forceinline__ buf_rsrc_t buf_rsrc(const void *p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T> __device__ __forceinline__ T buf_load(const buf_rsrc_t &r, uint32_t off, int soff);
+template <> __device__ __forceinline__ float buf_load<float>(const buf_rsrc_t &r, uint32_t off, int soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, soff, 0));
+}
+template <> __device__ __forceinline__ double buf_load<double>(const buf_rsrc_t &r, uint32_t off, int soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, soff, 0));
+}
+typedef unsigned buf_u2 __attribute__((ext_vector_type(2)));
+template <typename T> __device__ __forceinline__ void buf_store(T x, const buf_rsrc_t &r, uint32_t off, int soff);
+template <> __device__ __forceinline__ void buf_store<float>(float x, const buf_rsrc_t &r, uint32_t off, int soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, (int)off, soff, 0);
+}
+template <> __device__ __forceinline__ void buf_store<double>(double x, const buf_rsrc_t &r, uint32_t off, int soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(buf_u2, x), r, (int)off, soff, 0);
+}
+// Per-lane offset of a masked-off lane: beyond every descriptor of the VALU kernel (its
+// output arrays stay below 2 GiB).
+constexpr uint32_t kBufOff = 0x80000000u;
+
 template <typename T>
 struct FluxArgs {
     const T *Us, *Um, *Gs, *Gm, *met;
@@ -88,11 +120,12 @@ struct TileCursor {
     __device__ void next() { k += stride; }
 };
 
-// LDS bytes of a tile with capacity tf faces.
+// LDS bytes of a tile with capacity tf faces: per side, variable and node a row of 2 tf + 2
+// mortar slots plus two columns that absorb the writes of dead projection items.
 template <typename T, int NP, int VS, int VM>
 constexpr size_t tile_lds(int tf)
 {
-    return (size_t)(VS + VM) * NP * (2 * tf + 2) * sizeof(T) + (size_t)8 * NP * NP * sizeof(T);
+    return (size_t)(VS + VM) * NP * (2 * tf + 4) * sizeof(T) + (size_t)8 * NP * NP * sizeof(T);
 }
 
 // Tile capacity: among the capacities whose LDS fits the budget, the one that best fills
@@ -123,12 +156,12 @@ struct FluxCfg {
     static constexpr int VS = V + (MET ? 4 : 0);   // the static side also carries metrics
     static constexpr int NN = NP * NP;
     static constexpr int TF = pick_tile<T, NP, VS, V>(BUDGET);
-    static constexpr int LD = 2 * TF + 2;
+    static constexpr int LD = 2 * TF + 4;           // row length; columns 2TF+2, 2TF+3: dead writes
     static constexpr int NIT_S = VS * (TF + 1);
     static constexpr int NIT_M = V * (TF + 1);
     static constexpr int ITEMS = ((NIT_S > NIT_M ? NIT_S : NIT_M) + kHalf - 1) / kHalf;
     static constexpr int ROUNDS = ((2 * TF + 1) * NP + kFluxThreads - 1) / kFluxThreads;
-    static constexpr int ITEMS3 = (10 * TF + kFluxThreads - 1) / kFluxThreads;  // back projection
+    static constexpr int ITEMS3 = (5 * TF + kHalf - 1) / kHalf;   // back projection, per side
     static constexpr int LDS_T = (VS + V) * NP * LD;    // state region (elements of T)
 };
 
@@ -149,35 +182,33 @@ __device__ __forceinline__ TileGeom tile_geom(const FluxArgs<T> &a, int t, int N
     return g;
 }
 
-// Phase 0, in two steps: the face columns of the items this thread projects (loaded one
-// phase ahead), then the loads of their face lines.  Vector-memory operations complete
-// in issue order, so waiting for a column that was loaded long before costs nothing,
-// while a column loaded right before its use would also wait for every store and load
-// issued before it.
+// Phase 0, in two steps: the face columns of the items this thread projects, then the
+// loads of their face lines.  Every lane issues every load (clamped to a valid address,
+// the item marked dead) so that the number of vector-memory operations between a load
+// and its use is the same on every path: vector-memory operations complete in issue
+// order, and the compiler can then wait for exactly the operation it needs instead of
+// for all outstanding ones (a lookup issued after the previous tile's stores would
+// otherwise also wait for those stores).  The columns of a tile are looked up two tiles
+// ahead of its loads.  A column of a dead item (past the tile, or no tile at all) is
+// still a valid column; the item is recognised from the geometry where it is used (a
+// select on the loaded value here would let the compiler sink the load into a branch).
 template <typename C, typename T, int NP>
-__device__ __forceinline__ void prefetch_cols(const FluxArgs<T> &a, const TileGeom &g, int side,
-                                              int lt, int (&cols)[C::ITEMS])
+__device__ __forceinline__ void prefetch_cols(const FluxArgs<T> &a, const TileGeom &g, int side, int lt,
+                                              int (&cols)[C::ITEMS])
 {
     constexpr int TF = C::TF;
     const int np_ = a.n_par;
-    const int nit = side ? C::NIT_M : C::NIT_S;
+    const int32_t *fid = (side ? a.fid_m : a.fid_s) + (size_t)g.row * np_;
+    // static slot f: face i0 - 1 + f (slot 0 = halo); moving slot f: face i0 + f - n - 1
+    const int off = side ? -a.nmod - 1 : -1;
 #pragma unroll
     for (int k = 0; k < C::ITEMS; ++k) {
         const int it = lt + k * kHalf;
         const int v = it / (TF + 1);
         const int f = it - v * (TF + 1);
-        cols[k] = -1;
-        if (it < nit && f <= g.nf) {
-            if (!side) {                    // static slot f: face i0 - 1 + f (slot 0 = halo)
-                int i = g.i0 - 1 + f;
-                if (i < 0) i += np_;
-                cols[k] = a.fid_s[(size_t)g.row * np_ + i];
-            } else {                        // moving slot f: face i0 + f - n - 1
-                int jt = g.i0 + f - a.nmod - 1;
-                if (jt < 0) jt += np_;
-                cols[k] = a.fid_m[(size_t)g.row * np_ + jt];
-            }
-        }
+        int i = g.i0 + min(f, g.nf) + off;
+        if (i < 0) i += np_;
+        cols[k] = fid[i];
     }
 }
 
@@ -185,56 +216,40 @@ template <typename C, typename T, int NP>
 __device__ __forceinline__ void prefetch(const FluxArgs<T> &a, const TileGeom &g, int side, int lt,
                                          const int (&cols)[C::ITEMS], T (&u)[C::ITEMS][NP])
 {
-    constexpr int V = C::V, TF = C::TF;
+    constexpr int V = C::V, VS = C::VS, TF = C::TF;
     const size_t plane_s = (size_t)NP * NP * a.nfs, plane_m = (size_t)NP * NP * a.nfm;
+    const size_t stride = side ? a.nfm : a.nfs;
 #pragma unroll
     for (int k = 0; k < C::ITEMS; ++k) {
         const int it = lt + k * kHalf;
-        const int v = it / (TF + 1);
-        const bool ok = cols[k] >= 0;
-        const T *src = nullptr;
-        size_t stride = 0;
-        if (ok) {
-            if (!side) {
-                src = (v < 5 ? a.Us + v * plane_s
-                             : (v < V ? a.Gs + (v - 5) * plane_s : a.met + (v - V) * plane_s)) + cols[k];
-                stride = a.nfs;
-            } else {
-                src = (v < 5 ? a.Um + v * plane_m : a.Gm + (v - 5) * plane_m) + cols[k];
-                stride = a.nfm;
-            }
-        }
+        const int v = min(it / (TF + 1), side ? V - 1 : VS - 1);
+        const int c = cols[k];                      // dead items read a valid column
+        const T *src = !side ? (v < 5 ? a.Us + v * plane_s
+                                      : (v < V ? a.Gs + (v - 5) * plane_s : a.met + (v - V) * plane_s))
+                             : (v < 5 ? a.Um + v * plane_m : a.Gm + (v - 5) * plane_m);
+        src += c + (size_t)NP * g.pp * stride;
 #pragma unroll
-        for (int j = 0; j < NP; ++j) u[k][j] = ok ? src[(size_t)(j + NP * g.pp) * stride] : T(0);
+        for (int j = 0; j < NP; ++j) u[k][j] = src[(size_t)j * stride];
     }
 }
 
-// Output face columns of the back-projection items of this thread (item it = tid + k*256:
-// side, variable, face f of the tile), -1 where the item does not exist.
+// Output face columns of this thread's back-projection items (item e = lt + k*128 of its
+// side: variable e / TF, face f = e % TF of the tile); unconditional loads, as above.
 template <typename C, typename T>
-__device__ __forceinline__ void out_cols(const FluxArgs<T> &a, const TileGeom &g, int tid,
+__device__ __forceinline__ void out_cols(const FluxArgs<T> &a, const TileGeom &g, int side, int lt,
                                          int (&col3)[C::ITEMS3])
 {
     constexpr int TF = C::TF;
     const int np_ = a.n_par;
+    const int32_t *fid = (side ? a.fid_m : a.fid_s) + (size_t)g.row * np_;
+    const int off = side ? -a.nmod - 1 : 0;   // moving face i0+f-n-1, static face i0+f
 #pragma unroll
     for (int k = 0; k < C::ITEMS3; ++k) {
-        const int it = tid + k * kFluxThreads;
-        col3[k] = -1;
-        if (it < 10 * TF) {
-            const int sd = it >= 5 * TF;
-            const int e = sd ? it - 5 * TF : it;
-            const int f = e - (e / TF) * TF;
-            if (f < g.nf) {
-                if (sd) {
-                    int jt = g.i0 + f - a.nmod - 1;
-                    if (jt < 0) jt += np_;
-                    col3[k] = a.fid_m[(size_t)g.row * np_ + jt];
-                } else {
-                    col3[k] = a.fid_s[(size_t)g.row * np_ + g.i0 + f];
-                }
-            }
-        }
+        const int e = lt + k * kHalf;
+        const int f = e - (e / TF) * TF;
+        int i = g.i0 + min(f, g.nf - 1) + off;
+        if (i < 0) i += np_;
+        col3[k] = fid[i];
     }
 }
 
@@ -263,63 +278,93 @@ __device__ __forceinline__ void run_interface(const FluxArgs<T> &a, TileCursor &
     T *ldsF = lds;                          // fluxes [5][NP][LD] (reuses the static region)
 
     const int tid = threadIdx.x;
-    const int side = tid >= kHalf;          // 0: static, 1: moving (phases 0, 1)
+    // 0: static, 1: moving (phases 0, 1, 3); uniform over each wave
+    const int side = __builtin_amdgcn_readfirstlane(tid >= kHalf ? 1 : 0);
     const int lt = tid - side * kHalf;
     const int np_ = a.n_par;
     const int nmod = a.nmod;
     const size_t plane_s = (size_t)P * a.nfs, plane_m = (size_t)P * a.nfm;
 
+    // Pipeline: the face lines of tile t+1 are loaded while tile t is processed; at the
+    // start of tile t the input columns of tile t+2 and the output columns of tile t+1
+    // are looked up, so every column is in registers before the loads that retire it are
+    // waited for.
+    const buf_rsrc_t rF = side ? buf_rsrc(a.Fm, (uint32_t)(5 * plane_m * sizeof(T)))
+                               : buf_rsrc(a.Fs, (uint32_t)(5 * plane_s * sizeof(T)));
+    const uint32_t nfo = side ? a.nfm : a.nfs;
     TileGeom g = tile_geom(a, cur.tile(), NP);
+    cur.next();
+    bool more = cur.valid();
+    TileGeom gn = tile_geom(a, more ? cur.tile() : 0, NP);
     T u[C::ITEMS][NP];
-    int cols[C::ITEMS], col3[C::ITEMS3];
+    int cols[C::ITEMS], cols_n[C::ITEMS], col3[C::ITEMS3], col3_n[C::ITEMS3];
     prefetch_cols<C, T, NP>(a, g, side, lt, cols);
+    out_cols<C, T>(a, g, side, lt, col3);
+    prefetch_cols<C, T, NP>(a, gn, side, lt, cols_n);
     prefetch<C, T, NP>(a, g, side, lt, cols, u);
+    // Stores that write nothing, in the place of the previous tile's: the loop is then
+    // entered with the same sequence of outstanding memory operations as it is repeated
+    // with, and the compiler's wait for a tile's loads need not also cover the previous
+    // tile's stores.
+#pragma unroll
+    for (int k = 0; k < C::ITEMS3 * NP; ++k)   // distinct offsets: no store is merged away
+        buf_store<T>(T(0), rF, kBufOff + (uint32_t)(k * sizeof(T)), 0);
 
     // FP64 matrices for this stage, once per workgroup and interface
     assemble_matrices<NP, T>(a.basis, a.s, reinterpret_cast<double *>(lds), nullptr, nullptr,
                              mats, mats + 4 * NN);
 
     while (true) {
-        // this tile's output columns and the next tile's input columns, early
-        out_cols<C, T>(a, g, tid, col3);
         cur.next();
-        const bool more = cur.valid();
-        TileGeom gn = g;
-        if (more) {
-            gn = tile_geom(a, cur.tile(), NP);
-            prefetch_cols<C, T, NP>(a, gn, side, lt, cols);
-        }
+        const bool more2 = cur.valid();
+        const TileGeom gnn = tile_geom(a, more2 ? cur.tile() : 0, NP);
+        prefetch_cols<C, T, NP>(a, gnn, side, lt, cols);
+        out_cols<C, T>(a, gn, side, lt, col3_n);
         // ---- phase 1: forward projection (register mat-vec) ------------------------
         {
             // static: Pf0 -> slot 2f-1 (column 2f), Pf1 -> slot 2f (column 2f+1)
             // moving: Pf3 (lower part) -> slot 2f (column 2f), Pf2 (upper) -> slot 2f+1
+            // Every item is projected (no branch, so each matrix row is read once for all
+            // of this thread's items) and written as one pair (columns 2f, 2f+1): the
+            // static column 0 and the columns of faces past the tile are never read, and
+            // items past the last variable write the two spare columns of the last one.
             const T *PA = mats + (side ? 3 : 0) * NN;
             const T *PB = mats + (side ? 2 : 1) * NN;
             T *base = side ? ldsM : ldsS;
             const int nit = side ? C::NIT_M : C::NIT_S;
+            const int vlast = side ? V - 1 : VS - 1;
+            int woff[C::ITEMS];
 #pragma unroll
             for (int k = 0; k < C::ITEMS; ++k) {
                 const int it = lt + k * kHalf;
                 const int v = it / (TF + 1);
                 const int f = it - v * (TF + 1);
-                if (it < nit && f <= g.nf) {
-                    T *dst = base + v * NP * LD;
+                woff[k] = it < nit ? v * NP * LD + 2 * f : vlast * NP * LD + 2 * TF + 2;
+            }
+            typedef T T2 __attribute__((ext_vector_type(2)));
 #pragma unroll
-                    for (int q = 0; q < NP; ++q) {
-                        T qa = T(0), qb = T(0);
+            for (int q = 0; q < NP; ++q) {
+                T pa[NP], pb[NP];
 #pragma unroll
-                        for (int j = 0; j < NP; ++j) {
-                            qa += PA[q * NP + j] * u[k][j];
-                            qb += PB[q * NP + j] * u[k][j];
-                        }
-                        if (side || f >= 1) dst[q * LD + 2 * f] = qa;
-                        dst[q * LD + 2 * f + 1] = qb;
+                for (int j = 0; j < NP; ++j) {
+                    pa[j] = PA[q * NP + j];
+                    pb[j] = PB[q * NP + j];
+                }
+#pragma unroll
+                for (int k = 0; k < C::ITEMS; ++k) {
+                    T qa = T(0), qb = T(0);
+#pragma unroll
+                    for (int j = 0; j < NP; ++j) {
+                        qa += pa[j] * u[k][j];
+                        qb += pb[j] * u[k][j];
                     }
+                    *reinterpret_cast<T2 *>(base + woff[k] + q * LD) = T2{qa, qb};
                 }
             }
         }
-        // the next tile's loads fly while this tile's flux and back projection run
-        if (more) prefetch<C, T, NP>(a, gn, side, lt, cols, u);
+        // the next tile's loads fly while this tile's flux and back projection run (dead
+        // loads after the last tile)
+        prefetch<C, T, NP>(a, gn, side, lt, cols_n, u);
         __syncthreads();
 
         // ---- phase 2: flux at every mortar node -------------------------------------
@@ -375,48 +420,53 @@ __device__ __forceinline__ void run_interface(const FluxArgs<T> &a, TileCursor &
         }
         __syncthreads();
 
-        // ---- phase 3: back projection onto both sides -------------------------------
-        const T *Pb = mats + 4 * NN;
+        // ---- phase 3: back projection, threads 0-127 static, 128-255 moving ----------
+        // static face i0+f: mortars (i0+f, 0) slot 2f+1 and (i0+f, 1) slot 2f+2
+        // moving face i0+f-n-1: lower (i0+f-1, 1) slot 2f, upper (i0+f, 0) slot 2f+1
+        {
+            const T *B_lo = mats + 4 * NN + (side ? 3 : 0) * NN;
+            const T *B_hi = mats + 4 * NN + (side ? 2 : 1) * NN;
 #pragma unroll
-        for (int k3 = 0; k3 < C::ITEMS3; ++k3) {
-            const int it = tid + k3 * kFluxThreads;
-            if (col3[k3] < 0) continue;
-            const int sd = it >= 5 * TF;
-            const int e = sd ? it - 5 * TF : it;
-            const int v = e / TF;
-            const int f = e - v * TF;
-            const T *src = ldsF + v * NP * LD;
-            // static face i0+f: mortars (i0+f, 0) slot 2f+1 and (i0+f, 1) slot 2f+2
-            // moving face i0+f-n-1: lower (i0+f-1, 1) slot 2f, upper (i0+f, 0) slot 2f+1
-            const int s0 = sd ? 2 * f : 2 * f + 1;
-            T lo[NP], hi[NP];
+            for (int k3 = 0; k3 < C::ITEMS3; ++k3) {
+                // the matrices are read again for every item: kept in registers across
+                // items they would take 2 NP^2 of them
+                asm volatile("" ::: "memory");
+                const int e = lt + k3 * kHalf;
+                const int ve = e / TF;
+                const int f = e - ve * TF;
+                const int v = min(ve, 4);
+                const T *src = ldsF + v * NP * LD;
+                const int s0 = side ? 2 * f : 2 * f + 1;
+                T lo[NP], hi[NP];
 #pragma unroll
-            for (int q = 0; q < NP; ++q) {
-                lo[q] = src[q * LD + s0];
-                hi[q] = src[q * LD + s0 + 1];
-            }
-            const T *B_lo = Pb + (sd ? 3 : 0) * NN;
-            const T *B_hi = Pb + (sd ? 2 : 1) * NN;
-            T *dst;
-            size_t stride;
-            if (sd) {
-                dst = a.Fm + v * plane_m + col3[k3];
-                stride = a.nfm;
-            } else {
-                dst = a.Fs + v * plane_s + col3[k3];
-                stride = a.nfs;
-            }
+                for (int q = 0; q < NP; ++q) {
+                    lo[q] = src[q * LD + s0];
+                    hi[q] = src[q * LD + s0 + 1];
+                }
+                // every lane stores; a dead item's offset lies beyond the array
+                const bool ok = e < 5 * TF && f < g.nf;
+                const uint32_t o0 = ((uint32_t)(v * NN + NP * g.pp) * nfo + (uint32_t)col3[k3]) * (uint32_t)sizeof(T);
 #pragma unroll
-            for (int j = 0; j < NP; ++j) {
-                T acc = T(0);
+                for (int j = 0; j < NP; ++j) {
+                    T acc = T(0);
 #pragma unroll
-                for (int q = 0; q < NP; ++q) acc += B_lo[j * NP + q] * lo[q] + B_hi[j * NP + q] * hi[q];
-                dst[(size_t)(j + NP * g.pp) * stride] = acc;
+                    for (int q = 0; q < NP; ++q) {
+                        acc += B_lo[j * NP + q] * lo[q];   // contracted to one FMA each
+                        acc += B_hi[j * NP + q] * hi[q];
+                    }
+                    buf_store<T>(acc, rF, ok ? o0 + (uint32_t)(j * sizeof(T)) * nfo : kBufOff, 0);
+                }
             }
         }
         __syncthreads();   // phase 3 reads the LDS that the next phase 1 overwrites
         if (!more) break;
         g = gn;
+        gn = gnn;
+        more = more2;
+#pragma unroll
+        for (int k = 0; k < C::ITEMS; ++k) cols_n[k] = cols[k];
+#pragma unroll
+        for (int k = 0; k < C::ITEMS3; ++k) col3[k] = col3_n[k];
     }
 }
 

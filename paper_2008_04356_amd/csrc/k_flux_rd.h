@@ -146,34 +146,6 @@ __device__ __forceinline__ double rd_right(double x)
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// Buffer access (bit patterns, no conversion) with a 32-bit per-lane byte offset and a scalar byte offset (the
-// variable's plane).  Word 3 of the descriptor: 32-bit data format, no swizzle, raw
-// addressing; accesses at or beyond num_records bytes read 0 and write nothing.
-typedef __amdgpu_buffer_rsrc_t rd_rsrc_t;
-__device__ __forceinline__ rd_rsrc_t rd_rsrc(const void *p, uint32_t bytes)
-{
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
-}
-template <typename T> __device__ __forceinline__ T rd_load(const rd_rsrc_t &r, uint32_t off, int soff);
-template <> __device__ __forceinline__ float rd_load<float>(const rd_rsrc_t &r, uint32_t off, int soff)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, soff, 0));
-}
-template <> __device__ __forceinline__ double rd_load<double>(const rd_rsrc_t &r, uint32_t off, int soff)
-{
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, soff, 0));
-}
-typedef unsigned rd_u2 __attribute__((ext_vector_type(2)));
-template <typename T> __device__ __forceinline__ void rd_store(T x, const rd_rsrc_t &r, uint32_t off, int soff);
-template <> __device__ __forceinline__ void rd_store<float>(float x, const rd_rsrc_t &r, uint32_t off, int soff)
-{
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, (int)off, soff, 0);
-}
-template <> __device__ __forceinline__ void rd_store<double>(double x, const rd_rsrc_t &r, uint32_t off, int soff)
-{
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(rd_u2, x), r, (int)off, soff, 0);
-}
-
 // fp16 operands: a power-of-two scale per wave and operand set keeps the values in the
 // normal range of fp16 (surface elements of fine meshes push fluxes below 6e-5, where
 // fp16 loses precision and then flushes to zero).  Scaling by powers of two is exact, so
@@ -330,30 +302,31 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
     // buffer resources of the arrays (each below 4 GiB; the host checks this)
     const int pbytes_s = (int)((size_t)P * a.nfs * sizeof(T));
     const int pbytes_m = (int)((size_t)P * a.nfm * sizeof(T));
-    const rd_rsrc_t rU_s = rd_rsrc(a.Us, 5u * (uint32_t)pbytes_s);
-    const rd_rsrc_t rU_m = rd_rsrc(a.Um, 5u * (uint32_t)pbytes_m);
-    const rd_rsrc_t rG_s = rd_rsrc(a.Gs, NSV ? 15u * (uint32_t)pbytes_s : 0u);
-    const rd_rsrc_t rG_m = rd_rsrc(a.Gm, NSV ? 15u * (uint32_t)pbytes_m : 0u);
-    const rd_rsrc_t rMet = rd_rsrc(a.met, MET ? 4u * (uint32_t)pbytes_s : 0u);
-    const rd_rsrc_t rF_s = rd_rsrc(a.Fs, 5u * (uint32_t)pbytes_s);
-    const rd_rsrc_t rF_m = rd_rsrc(a.Fm, 5u * (uint32_t)pbytes_m);
+    const buf_rsrc_t rU_s = buf_rsrc(a.Us, 5u * (uint32_t)pbytes_s);
+    const buf_rsrc_t rU_m = buf_rsrc(a.Um, 5u * (uint32_t)pbytes_m);
+    const buf_rsrc_t rG_s = buf_rsrc(a.Gs, NSV ? 15u * (uint32_t)pbytes_s : 0u);
+    const buf_rsrc_t rG_m = buf_rsrc(a.Gm, NSV ? 15u * (uint32_t)pbytes_m : 0u);
+    const buf_rsrc_t rMet = buf_rsrc(a.met, MET ? 4u * (uint32_t)pbytes_s : 0u);
+    const buf_rsrc_t rF_s = buf_rsrc(a.Fs, 5u * (uint32_t)pbytes_s);
+    const buf_rsrc_t rF_m = buf_rsrc(a.Fm, 5u * (uint32_t)pbytes_m);
 
     // ---- per-tile operand fetch ---------------------------------------------------
     // One 32-bit byte offset per K value, shared by all variables (the variable's plane
     // is the scalar offset).  Padding K values and columns outside the tile read node 0
     // of a valid face: their A entries are zero or their columns are never used.
     T ls[VS][LF], lm[V][LM];
-    // column of this lane's static / moving face in tile g (a valid column also for
-    // lanes past the tile)
+    // column of this lane's static / moving face in tile g: every lane loads (lanes past
+    // the tile the column of the tile's last face), so the number of memory operations
+    // between a lookup and its use does not depend on the path taken
     auto col_s = [&](const TileGeom &g) {
-        int i = g.i0 - 1 + col;
+        int i = g.i0 - 1 + min(col, g.nf);
         if (i < 0) i += np_;
-        return col <= g.nf ? a.fid_s[(size_t)g.row * np_ + i] : 0;
+        return a.fid_s[(size_t)g.row * np_ + i];
     };
     auto col_m = [&](const TileGeom &g) {
-        int jt = g.i0 + col - nmod - 1;
+        int jt = g.i0 + min(col, g.nf) - nmod - 1;
         if (jt < 0) jt += np_;
-        return col <= g.nf ? a.fid_m[(size_t)g.row * np_ + jt] : 0;
+        return a.fid_m[(size_t)g.row * np_ + jt];
     };
     auto fetch_s = [&](const TileGeom &g, int cs_) {
         const uint32_t cs = (uint32_t)cs_, line = (uint32_t)(NP * g.pp);
@@ -367,10 +340,10 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
             }
 #pragma unroll
         for (int v = 0; v < VS; ++v) {
-            const rd_rsrc_t &rs = v < 5 ? rU_s : (v < V ? rG_s : rMet);
+            const buf_rsrc_t &rs = v < 5 ? rU_s : (v < V ? rG_s : rMet);
             const int pv = v < 5 ? v : (v < V ? v - 5 : v - V);
 #pragma unroll
-            for (int q = 0; q < LF; ++q) ls[v][q] = rd_load<T>(rs, os[q], pv * pbytes_s);
+            for (int q = 0; q < LF; ++q) ls[v][q] = buf_load<T>(rs, os[q], pv * pbytes_s);
         }
     };
     auto fetch_m = [&](const TileGeom &g, int cm_) {
@@ -386,10 +359,10 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
             }
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            const rd_rsrc_t &rs = v < 5 ? rU_m : rG_m;
+            const buf_rsrc_t &rs = v < 5 ? rU_m : rG_m;
             const int pv = v < 5 ? v : v - 5;
 #pragma unroll
-            for (int q = 0; q < LM; ++q) lm[v][q] = rd_load<T>(rs, om[q], pv * pbytes_m);
+            for (int q = 0; q < LM; ++q) lm[v][q] = buf_load<T>(rs, om[q], pv * pbytes_m);
         }
     };
     auto proj_s = [&](const T (&b)[LF], acc_t (&d)[RB]) {
@@ -470,23 +443,31 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
     // compiler from interleaving all of them (which multiplies the live temporaries).
     // A tile's loads are issued at its start and the other waves of the SIMD cover their
     // latency.  The face columns of the next tile are looked up at the start of the
-    // current one: vector-memory operations complete in issue order, so a column loaded
-    // right before the loads that need it would also wait for the previous tile's stores.
+    // current one, before its loads: vector-memory operations complete in issue order,
+    // so the current tile's loads (waited for anyway) retire the lookup, while a lookup
+    // issued after the previous tile's stores would also wait for them.
     WaveCursor cur(a.n_tiles, C::WAVES, wave);
     bool more = cur.valid();
     TileGeom g = tile_geom(a, more ? cur.tile() : 0, NP);
-    int cs_n = more ? col_s(g) : 0, cm_n = more ? col_m(g) : 0;
+    int cs_c = col_s(g), cm_c = col_m(g);
+    // the first columns are waited for here, so that the loop is entered, like every later
+    // iteration, with no lookup outstanding
+    asm volatile("" ::"v"(cs_c), "v"(cm_c));
     while (more) {
         const TileGeom gc = g;
-        fetch_s(gc, cs_n);
-        fetch_m(gc, cm_n);
         cur.next();
         more = cur.valid();
-        if (more) {
-            g = tile_geom(a, cur.tile(), NP);
-            cs_n = col_s(g);
-            cm_n = col_m(g);
-        }
+        g = tile_geom(a, more ? cur.tile() : 0, NP);   // tile 0: a dead lookup
+        const int cs_n = col_s(g), cm_n = col_m(g);
+        // this tile's columns: the static face of slot col and the moving face of slot
+        // col are also the faces this lane writes
+        const int oc_s = cs_c, oc_m = cm_c;
+        fetch_s(gc, oc_s);
+        fetch_m(gc, oc_m);
+        // every load of the tile is issued before the first is used
+        __builtin_amdgcn_sched_barrier(0);
+        cs_c = cs_n;
+        cm_c = cm_n;
         acc_t QL[5][RB], QR[5][RB], MT[MET ? 4 : 1][RB];
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
@@ -591,13 +572,6 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
         // ---- back projection onto both sides ----------------------------------------
         const bool out_s = col >= 1 && col <= gc.nf;       // static face i0-1+col
         const bool out_m = col < gc.nf;                    // moving face of slot col
-        int oc_s = 0, oc_m = 0;
-        if (out_s) oc_s = a.fid_s[(size_t)gc.row * np_ + gc.i0 - 1 + col];
-        if (out_m) {
-            int j2 = gc.i0 + col - nmod - 1;
-            if (j2 < 0) j2 += np_;
-            oc_m = a.fid_m[(size_t)gc.row * np_ + j2];
-        }
         const uint32_t line = (uint32_t)(NP * gc.pp);
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
@@ -679,17 +653,19 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
                     dm[r] += corr_m;
                 }
             }
+            // every lane stores (no branch: a branch around a store leaves the compiler
+            // unsure how many memory operations are outstanding, and it then waits for all
+            // of them before the next); masked lanes get an offset beyond the array
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int j = Op::row(kq, r);
-                if (j < NP) {
-                    if (out_s)
-                        rd_store<T>(T(ds[r]), rF_s, ((line + j) * (uint32_t)a.nfs + oc_s) * (uint32_t)sizeof(T),
-                                    v * pbytes_s);
-                    if (out_m)
-                        rd_store<T>(T(dm[r]), rF_m, ((line + j) * (uint32_t)a.nfm + oc_m) * (uint32_t)sizeof(T),
-                                    v * pbytes_m);
-                }
+                const uint32_t jj = (uint32_t)min(j, NP - 1);
+                const uint32_t o_s = ((line + jj) * (uint32_t)a.nfs + (uint32_t)oc_s) * (uint32_t)sizeof(T) +
+                                     (uint32_t)(v * pbytes_s);
+                const uint32_t o_m = ((line + jj) * (uint32_t)a.nfm + (uint32_t)oc_m) * (uint32_t)sizeof(T) +
+                                     (uint32_t)(v * pbytes_m);
+                buf_store<T>(T(ds[r]), rF_s, out_s && j < NP ? o_s : kBufOff, 0);
+                buf_store<T>(T(dm[r]), rF_m, out_m && j < NP ? o_m : kBufOff, 0);
             }
         }
     }

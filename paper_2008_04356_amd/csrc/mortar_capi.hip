@@ -217,6 +217,16 @@ static bool rd_addressable(const mortar_iface_desc &d)
     return vars * P * nf * elem < ((int64_t)1 << 32);
 }
 
+// The VALU-projection kernels store through buffer descriptors over one side's five
+// flux planes and mask lanes with an offset of 2 GiB: each flux array must stay below it.
+static bool valu_addressable(const mortar_iface_desc &d)
+{
+    const int64_t P = (int64_t)(d.N + 1) * (d.N + 1);
+    const int64_t elem = d.precision == MORTAR_FP64 ? 8 : 4;
+    const int64_t nf = std::max<int64_t>(d.n_face_static, d.n_face_moving);
+    return 5 * P * nf * elem < ((int64_t)1 << 31);
+}
+
 static int validate_one(const mortar_iface_desc &d)
 {
     if (d.N < 1 || d.n_par < 1 || d.n_perp < 1) return MORTAR_ERR_INVALID_ARG;
@@ -324,7 +334,7 @@ static bool variant_allowed(const Iface &f, int variant)
 {
     if (variant < 0 || variant > 3) return false;
     if (f.lp) return variant == 2;
-    if (variant == 3) return f.elem == 4;
+    if (variant == 0 || variant == 3) return valu_addressable(f.d) && (variant == 0 || f.elem == 4);
     return variant != 2 || rd_addressable(f.d);
 }
 
@@ -389,6 +399,7 @@ static int setup_one(const mortar_iface_desc &d, Iface &f)
         f.flux_variant = kname == "mfma" ? 1 : (kname == "rd" ? 2 : 0);
         if (f.lp) f.flux_variant = 2;
         if (!variant_allowed(f, f.flux_variant)) f.flux_variant = 0;
+        if (!variant_allowed(f, f.flux_variant)) f.flux_variant = 1;   // MFMA-LDS: any size
         f.flux_occ = variant_occupancy(f, f.flux_variant);
         (void)ns; (void)met; (void)riem;
     }
