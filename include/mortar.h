@@ -143,13 +143,16 @@ int mortar_graph_destroy(mortar_graph *g);
  * vector units, tiles staged in LDS), MORTAR_KERNEL_MFMA_LDS (projections as matrix-core
  * GEMMs, tiles staged in LDS), MORTAR_KERNEL_REGISTER (one wave per tile, GEMM results
  * kept in registers; the only variant of the bf16/fp16 precisions), MORTAR_KERNEL_VALU_WIDE
- * (FP32 only: the VALU kernel with 72 KB of LDS, longer tiles).  tile_len: output
+ * (FP32 only: the VALU kernel with 72 KB of LDS, longer tiles), MORTAR_KERNEL_HYBRID
+ * (FP32 only: tiles staged in LDS, both projections on the matrix cores over 16-face
+ * chunks, pointwise fluxes on the vector units; not for the largest degrees with
+ * metrics, whose tiles do not fit its LDS budget).  tile_len: output
  * faces per tile along the sliding direction (0 = the variant's largest; larger values
  * are capped to it).  grid: workgroups of the persistent launch (0 = every resident
  * slot of the device; otherwise at least 8, one per XCD).  Interfaces in one batched
  * launch share the VALU variant and the grid; each has its own tile_len. */
 enum { MORTAR_KERNEL_VALU = 0, MORTAR_KERNEL_MFMA_LDS = 1, MORTAR_KERNEL_REGISTER = 2,
-       MORTAR_KERNEL_VALU_WIDE = 3 };
+       MORTAR_KERNEL_VALU_WIDE = 3, MORTAR_KERNEL_HYBRID = 4 };
 typedef struct mortar_tuning {
     int32_t variant;
     int32_t tile_len;

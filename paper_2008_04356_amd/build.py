@@ -17,7 +17,7 @@ OUT = os.path.join(HERE, "libmortar.so")
 ARCH = os.environ.get("MORTAR_ARCH", "gfx950")
 
 SOURCES = ["mortar_capi.hip", "k_topology.hip", "k_flux_f32.hip", "k_flux_f64.hip",
-           "k_flux_wide_f32.hip",
+           "k_flux_wide_f32.hip", "k_flux_hyb_f32.hip",
            "k_flux_rd_f32.hip", "k_flux_rd_f64.hip", "k_flux_rd_bf16.hip",
            "k_flux_rd_fp16.hip", "k_flux_rd_batch_f32.hip",
            "k_flux_mfma_f32.hip", "k_flux_mfma_f64.hip", "k_flux_batch_f32.hip",
@@ -29,12 +29,12 @@ CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Wall", "-Wno-unused-function"]
 
 
-# The register-direct kernels keep matrix-core results in ordinary VGPRs (they feed the
-# vector units directly); not used for the FP64 unit, on which this compiler option
-# makes the compiler itself crash.
+# The register-direct and hybrid kernels keep matrix-core results in ordinary VGPRs
+# (they feed the vector units and LDS directly); not used for the FP64 unit, on which
+# this compiler option makes the compiler itself crash.
 EXTRA = {s: ["-mllvm", "-amdgpu-mfma-vgpr-form"]
          for s in ("k_flux_rd_f32.hip", "k_flux_rd_bf16.hip", "k_flux_rd_fp16.hip",
-                   "k_flux_rd_batch_f32.hip")}
+                   "k_flux_rd_batch_f32.hip", "k_flux_hyb_f32.hip")}
 
 
 def _compile(src):

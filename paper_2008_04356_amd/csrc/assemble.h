@@ -28,34 +28,36 @@ __device__ __forceinline__ void sub_map(int k, double s, double &slope, double &
     }
 }
 
-// All Lagrange basis values l_j(xi) of the nodes (barycentric second form, exact at nodes).
+// All Lagrange basis values l_j(xi) of the nodes, in the product form
+// l_j(xi) = bw_j prod_{m != j} (xi - x_m) with the barycentric weights bw_j: prefix and
+// suffix products, no division, exact (a zero factor) at the nodes themselves.
 template <int NP>
 __device__ __forceinline__ void lagrange_row(const BasisConsts *__restrict__ c, double xi,
                                              double (&l)[NP])
 {
-    int hit = -1;
+    double d[NP], pre[NP];
 #pragma unroll
-    for (int m = 0; m < NP; ++m)
-        if (xi == c->x[m]) hit = m;
-    if (hit >= 0) {
+    for (int m = 0; m < NP; ++m) d[m] = xi - c->x[m];
+    pre[0] = 1.0;
 #pragma unroll
-        for (int j = 0; j < NP; ++j) l[j] = (j == hit) ? 1.0 : 0.0;
-        return;
+    for (int m = 1; m < NP; ++m) pre[m] = pre[m - 1] * d[m - 1];
+    double suf = 1.0;
+#pragma unroll
+    for (int j = NP - 1; j >= 0; --j) {
+        l[j] = c->bw[j] * (pre[j] * suf);
+        suf *= d[j];
     }
-    double den = 0.0;
-#pragma unroll
-    for (int j = 0; j < NP; ++j) {
-        l[j] = c->bw[j] / (xi - c->x[j]);
-        den += l[j];
-    }
-    const double inv = 1.0 / den;
-#pragma unroll
-    for (int j = 0; j < NP; ++j) l[j] *= inv;
 }
 
-// Cooperative assembly by the threads of one block.  work: LDS scratch of at least
-// 8*NP*NP doubles.  Writes Pf64/Pb64 (each [4][NP][NP], may be null) and PfT/PbT in the
-// working precision (may be null).  Contains __syncthreads(): all threads must call it.
+// LDS scratch of the assembly, in doubles.
+template <int NP> constexpr int assemble_scratch() { return 8 * NP * NP; }
+
+// Cooperative assembly by the threads of one block: the basis rows at the mortar nodes
+// (Pf) and at the Gauss points of each sub-interval (Q), then every entry of
+// Pb_k = J_k Minv S_k with S_k[i][q] = sum_r tw_r Q_k[r][i] l_q(t_r) formed in place.
+// work: LDS scratch of assemble_scratch<NP>() doubles.  Writes Pf64/Pb64 (each
+// [4][NP][NP], may be null) and PfT/PbT in the working precision (may be null).
+// Contains __syncthreads(): all threads must call it.
 template <int NP, typename T>
 __device__ void assemble_matrices(const BasisConsts *__restrict__ c, double s, double *work,
                                   double *Pf64, double *Pb64, T *PfT, T *PbT)
@@ -80,7 +82,6 @@ __device__ void assemble_matrices(const BasisConsts *__restrict__ c, double s, d
         const int k = e / NN, j = (e % NN) / NP, q = e % NP;
         double a, b;
         sub_map(k, s, a, b);
-        // S_k[i][q] = sum_r tw_r Q_k[r][i] l_q(t_r);  Pb_k[j][q] = J_k sum_i Minv[j][i] S_k[i][q]
         double acc = 0.0;
 #pragma unroll
         for (int i = 0; i < NP; ++i) {

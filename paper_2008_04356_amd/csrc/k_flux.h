@@ -253,6 +253,71 @@ __device__ __forceinline__ void out_cols(const FluxArgs<T> &a, const TileGeom &g
     }
 }
 
+// Phase 2 of a tile, shared by the VALU- and the matrix-core-projection kernels: thread
+// <-> mortar node (all ROUNDS rounds of 256 points), all variables of both sides from
+// LDS (static slot ms at column ms + 1, moving slot ms at column ms, rows of LD), the
+// pointwise Riemann + BR1 flux times the surface element, written over the static
+// region as fluxes [5][NP][LD] (slot ms at column ms).  Starts after and ends with a
+// barrier.
+template <typename T, int NP, bool NSV, bool MET, int RIEM, int LD, int ROUNDS>
+__device__ __forceinline__ void flux_points(const FluxArgs<T> &a, int nf, const T *ldsS, const T *ldsM,
+                                            T *ldsF)
+{
+    constexpr int V = NSV ? 20 : 5;
+    const int tid = threadIdx.x;
+    const int nm = 2 * nf + 1;
+    const int npts = nm * NP;
+    T res[ROUNDS][5];
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+        const int pt = tid + r * kFluxThreads;
+        if (pt < npts) {
+            const int q = pt / nm;
+            const int ms = pt - q * nm;
+            T UL[5], UR[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                UL[v] = ldsS[(v * NP + q) * LD + ms + 1];
+                UR[v] = ldsM[(v * NP + q) * LD + ms];
+            }
+            T nx = a.nx, ny = a.ny, nz = a.nz, dS = a.dS;
+            if (MET) {
+                nx = ldsS[((V + 0) * NP + q) * LD + ms + 1];
+                ny = ldsS[((V + 1) * NP + q) * LD + ms + 1];
+                nz = ldsS[((V + 2) * NP + q) * LD + ms + 1];
+                dS = ldsS[((V + 3) * NP + q) * LD + ms + 1];
+            }
+            T F[5];
+            convective_flux<T, RIEM>(UL, UR, nx, ny, nz, a.gas, F);
+            if (NSV) {
+                T G[15], FvL[5], FvR[5];
+#pragma unroll
+                for (int gg = 0; gg < 15; ++gg) G[gg] = ldsS[((5 + gg) * NP + q) * LD + ms + 1];
+                viscous_flux(UL, G, nx, ny, nz, a.gas, FvL);
+#pragma unroll
+                for (int gg = 0; gg < 15; ++gg) G[gg] = ldsM[((5 + gg) * NP + q) * LD + ms];
+                viscous_flux(UR, G, nx, ny, nz, a.gas, FvR);
+#pragma unroll
+                for (int v = 0; v < 5; ++v) F[v] -= T(0.5) * (FvL[v] + FvR[v]);
+            }
+#pragma unroll
+            for (int v = 0; v < 5; ++v) res[r][v] = F[v] * dS;
+        }
+    }
+    __syncthreads();   // the flux region overwrites static values still being read
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+        const int pt = tid + r * kFluxThreads;
+        if (pt < npts) {
+            const int q = pt / nm;
+            const int ms = pt - q * nm;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) ldsF[(v * NP + q) * LD + ms] = res[r][v];
+        }
+    }
+    __syncthreads();
+}
+
 // LDS bytes of one instantiation (state region + matrices).
 template <typename T, int NP, bool NSV, bool MET, int BUDGET>
 constexpr size_t flux_smem_bytes()
@@ -269,7 +334,7 @@ __device__ __forceinline__ void run_interface(const FluxArgs<T> &a, TileCursor &
 {
     using C = FluxCfg<T, NP, NSV, MET, BUDGET>;
     constexpr int V = C::V, VS = C::VS, NN = C::NN, TF = C::TF, LD = C::LD, P = NN;
-    static_assert(C::LDS_T * sizeof(T) >= 8 * NN * sizeof(double), "assembly scratch");
+    static_assert(C::LDS_T * sizeof(T) >= assemble_scratch<NP>() * sizeof(double), "assembly scratch");
 
     T *lds = reinterpret_cast<T *>(smem);
     T *mats = reinterpret_cast<T *>(smem + ((size_t)C::LDS_T * sizeof(T) + 15) / 16 * 16);
@@ -368,57 +433,7 @@ __device__ __forceinline__ void run_interface(const FluxArgs<T> &a, TileCursor &
         __syncthreads();
 
         // ---- phase 2: flux at every mortar node -------------------------------------
-        const int nm = 2 * g.nf + 1;
-        const int npts = nm * NP;
-        T res[C::ROUNDS][5];
-#pragma unroll
-        for (int r = 0; r < C::ROUNDS; ++r) {
-            const int pt = tid + r * kFluxThreads;
-            if (pt < npts) {
-                const int q = pt / nm;
-                const int ms = pt - q * nm;
-                T UL[5], UR[5];
-#pragma unroll
-                for (int v = 0; v < 5; ++v) {
-                    UL[v] = ldsS[(v * NP + q) * LD + ms + 1];
-                    UR[v] = ldsM[(v * NP + q) * LD + ms];
-                }
-                T nx = a.nx, ny = a.ny, nz = a.nz, dS = a.dS;
-                if (MET) {
-                    nx = ldsS[((V + 0) * NP + q) * LD + ms + 1];
-                    ny = ldsS[((V + 1) * NP + q) * LD + ms + 1];
-                    nz = ldsS[((V + 2) * NP + q) * LD + ms + 1];
-                    dS = ldsS[((V + 3) * NP + q) * LD + ms + 1];
-                }
-                T F[5];
-                convective_flux<T, RIEM>(UL, UR, nx, ny, nz, a.gas, F);
-                if (NSV) {
-                    T G[15], FvL[5], FvR[5];
-#pragma unroll
-                    for (int gg = 0; gg < 15; ++gg) G[gg] = ldsS[((5 + gg) * NP + q) * LD + ms + 1];
-                    viscous_flux(UL, G, nx, ny, nz, a.gas, FvL);
-#pragma unroll
-                    for (int gg = 0; gg < 15; ++gg) G[gg] = ldsM[((5 + gg) * NP + q) * LD + ms];
-                    viscous_flux(UR, G, nx, ny, nz, a.gas, FvR);
-#pragma unroll
-                    for (int v = 0; v < 5; ++v) F[v] -= T(0.5) * (FvL[v] + FvR[v]);
-                }
-#pragma unroll
-                for (int v = 0; v < 5; ++v) res[r][v] = F[v] * dS;
-            }
-        }
-        __syncthreads();   // the flux region overwrites static values still being read
-#pragma unroll
-        for (int r = 0; r < C::ROUNDS; ++r) {
-            const int pt = tid + r * kFluxThreads;
-            if (pt < npts) {
-                const int q = pt / nm;
-                const int ms = pt - q * nm;
-#pragma unroll
-                for (int v = 0; v < 5; ++v) ldsF[(v * NP + q) * LD + ms] = res[r][v];
-            }
-        }
-        __syncthreads();
+        flux_points<T, NP, NSV, MET, RIEM, LD, C::ROUNDS>(a, g.nf, ldsS, ldsM, ldsF);
 
         // ---- phase 3: back projection, threads 0-127 static, 128-255 moving ----------
         // static face i0+f: mortars (i0+f, 0) slot 2f+1 and (i0+f, 1) slot 2f+2

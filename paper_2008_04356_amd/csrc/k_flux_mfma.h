@@ -73,7 +73,7 @@ __global__ __launch_bounds__((MCfg<T, NP, NSV, MET>::NT)) void k_mortar_flux_mfm
     using acc_t = typename M::acc;
     constexpr int V = C::V, VS = C::VS, NN = C::NN, TF = C::TF, LD = C::LD, P = NN;
     constexpr int NT = C::NT, NW = C::NW, KS = C::KS, RB = C::RB, KS3 = C::KS3;
-    static_assert(C::LDS_T * sizeof(T) >= 8 * NN * sizeof(double), "assembly scratch");
+    static_assert(C::LDS_T * sizeof(T) >= assemble_scratch<NP>() * sizeof(double), "assembly scratch");
 
     __shared__ __attribute__((aligned(16))) T lds[C::LDS_T];
     __shared__ T mats[8 * NN];

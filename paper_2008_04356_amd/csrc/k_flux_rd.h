@@ -674,7 +674,7 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
 template <typename T, int NP, bool NSV, bool MET, int RIEM, int PREC>
 __global__ __launch_bounds__(256) void k_mortar_flux_rd(FluxArgs<T> a)
 {
-    __shared__ double work[8 * NP * NP];
+    __shared__ double work[assemble_scratch<NP>()];
     __shared__ T mats[8 * NP * NP];          // Pf[4][NP][NP], Pb[4][NP][NP]
     __shared__ double wq[NP];
     rd_interface<T, NP, NSV, MET, RIEM, PREC>(a, work, mats, wq);
@@ -688,7 +688,7 @@ template <bool NSV, int RIEM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_mortar_flux_rd_batch(BatchArgs<float> b)
 {
     constexpr int NPM = 8;
-    __shared__ double work[8 * NPM * NPM];
+    __shared__ double work[assemble_scratch<NPM>()];
     __shared__ float mats[8 * NPM * NPM];
     __shared__ double wq[NPM];
     for (int i = 0; i < b.n_if; ++i) {

@@ -20,7 +20,7 @@ template <int NP>
 __global__ void k_assemble_inspect(const BasisConsts *__restrict__ basis, double s,
                                    char *__restrict__ params)
 {
-    __shared__ double work[8 * NP * NP];
+    __shared__ double work[assemble_scratch<NP>()];
     double *Pf = reinterpret_cast<double *>(params + kHeaderBytes);
     assemble_matrices<NP, double>(basis, s, work, Pf, Pf + 4 * NP * NP, (double *)nullptr,
                                   (double *)nullptr);

@@ -25,6 +25,10 @@ int flux_wide_tile_capacity_f32(int NP, bool ns, bool met);
 hipError_t launch_flux_wide_f32(const FluxArgs<float> &a, int NP, int grid, bool ns, bool met,
                                 int riem, hipStream_t st);
 int flux_occupancy_f64(int NP, bool ns, bool met, int riem);
+int flux_hyb_occupancy_f32(int NP, bool ns, bool met, int riem);
+int flux_hyb_tile_capacity_f32(int NP, bool ns, bool met);
+hipError_t launch_flux_hyb_f32(const FluxArgs<float> &a, int NP, int grid, bool ns, bool met,
+                               int riem, hipStream_t st);
 int flux_mfma_occupancy_f32(int NP, bool ns, bool met, int riem);
 int flux_mfma_occupancy_f64(int NP, bool ns, bool met, int riem);
 hipError_t launch_flux_mfma_f32(const FluxArgs<float> &a, int NP, int grid, bool ns, bool met,
@@ -325,6 +329,7 @@ static int variant_occupancy(const Iface &f, int variant)
         return f.elem == 8 ? flux_mfma_occupancy_f64(f.NP, ns, met, riem)
                            : flux_mfma_occupancy_f32(f.NP, ns, met, riem);
     if (variant == 3) return flux_wide_occupancy_f32(f.NP, ns, met, riem);
+    if (variant == 4) return flux_hyb_occupancy_f32(f.NP, ns, met, riem);
     if (f.lp == 1) return flux_rd_occupancy_bf16(f.NP, ns, met, riem);
     if (f.lp == 2) return flux_rd_occupancy_fp16(f.NP, ns, met, riem);
     return f.elem == 8 ? flux_rd_occupancy_f64(f.NP, ns, met, riem) : flux_rd_occupancy_f32(f.NP, ns, met, riem);
@@ -332,8 +337,11 @@ static int variant_occupancy(const Iface &f, int variant)
 
 static bool variant_allowed(const Iface &f, int variant)
 {
-    if (variant < 0 || variant > 3) return false;
+    if (variant < 0 || variant > 4) return false;
     if (f.lp) return variant == 2;
+    if (variant == 4)
+        return f.elem == 4 && valu_addressable(f.d) &&
+               flux_hyb_tile_capacity_f32(f.NP, f.d.physics == MORTAR_NAVIER_STOKES, f.d_metrics != nullptr) > 0;
     if (variant == 0 || variant == 3) return valu_addressable(f.d) && (variant == 0 || f.elem == 4);
     return variant != 2 || rd_addressable(f.d);
 }
@@ -396,7 +404,7 @@ static int setup_one(const mortar_iface_desc &d, Iface &f)
         const char *kv = std::getenv("MORTAR_FLUX_KERNEL");
         const std::string kname = kv ? kv : "";
         f.lp = d.precision == MORTAR_BF16_MFMA ? 1 : (d.precision == MORTAR_FP16_MFMA ? 2 : 0);
-        f.flux_variant = kname == "mfma" ? 1 : (kname == "rd" ? 2 : 0);
+        f.flux_variant = kname == "mfma" ? 1 : kname == "rd" ? 2 : kname == "hyb" ? 4 : 0;
         if (f.lp) f.flux_variant = 2;
         if (!variant_allowed(f, f.flux_variant)) f.flux_variant = 0;
         if (!variant_allowed(f, f.flux_variant)) f.flux_variant = 1;   // MFMA-LDS: any size
@@ -844,6 +852,7 @@ static int vmax_tile(const Iface &f, int variant)
 {
     const bool ns = f.d.physics == MORTAR_NAVIER_STOKES, met = f.d_metrics != nullptr;
     if (variant == 3) return flux_wide_tile_capacity_f32(f.NP, ns, met);
+    if (variant == 4) return flux_hyb_tile_capacity_f32(f.NP, ns, met);
     if (variant != 0) return 15;
     return f.elem == 8 ? flux_tile_capacity_f64(f.NP, ns, met) : flux_tile_capacity_f32(f.NP, ns, met);
 }
@@ -935,7 +944,7 @@ int mortar_autotune(mortar_handle *h, const void *const *U_s, const void *const 
         };
         int best_v = f.flux_variant, best_t = f.tune_tile;
         float best = 1e30f;
-        for (int v = 0; v <= 3; ++v) {
+        for (int v = 0; v <= 4; ++v) {
             if (!variant_allowed(f, v)) continue;
             f.flux_variant = v;
             f.flux_occ = variant_occupancy(f, v);
@@ -1015,6 +1024,7 @@ void fill_args(const Iface &f, const void *Us, const void *Um, const void *Gs,
     const double kfac = ns ? f.d.mu * f.d.gamma / (gm1 * f.d.Pr) : 0.0;
     const int64_t np = f.d.n_par;
     int cap = f.flux_variant == 3 ? flux_wide_tile_capacity_f32(f.NP, ns, met)
+            : f.flux_variant == 4 ? flux_hyb_tile_capacity_f32(f.NP, ns, met)
             : f.flux_variant != 0 ? 15
             : (f.elem == 8 ? flux_tile_capacity_f64(f.NP, ns, met)
                            : flux_tile_capacity_f32(f.NP, ns, met));
@@ -1083,6 +1093,7 @@ hipError_t launch_flux(const Iface &f, int n_cu, const void *Us, const void *Um,
     fill_args(f, Us, Um, Gs, Gm, Fs, Fm, a, n_tiles);
     const int grid = grid_of(n_tiles);
     if (f.flux_variant == 3) return launch_flux_wide_f32(a, f.NP, grid, ns, met, riem, st);
+    if (f.flux_variant == 4) return launch_flux_hyb_f32(a, f.NP, grid, ns, met, riem, st);
     return f.flux_variant == 1 ? launch_flux_mfma_f32(a, f.NP, grid, ns, met, riem, st)
                                : launch_flux_f32(a, f.NP, grid, ns, met, riem, st);
 }

@@ -47,7 +47,7 @@ class mortar_tuning(C.Structure):
                 ("reserved", C.c_int32)]
 
 
-KERNEL_VALU, KERNEL_MFMA_LDS, KERNEL_REGISTER, KERNEL_VALU_WIDE = 0, 1, 2, 3
+KERNEL_VALU, KERNEL_MFMA_LDS, KERNEL_REGISTER, KERNEL_VALU_WIDE, KERNEL_HYBRID = 0, 1, 2, 3, 4
 
 
 class MortarError(RuntimeError):

@@ -49,7 +49,8 @@ def test_single_interface_every_variant_and_tile(M):
         n, s = O.decompose(disp[0], spec.l_par)
         ref = H.oracle_flux(spec, oins[0], n, s)
         per_variant = {}
-        for variant in (M.KERNEL_VALU, M.KERNEL_MFMA_LDS, M.KERNEL_REGISTER, M.KERNEL_VALU_WIDE):
+        for variant in (M.KERNEL_VALU, M.KERNEL_MFMA_LDS, M.KERNEL_REGISTER, M.KERNEL_VALU_WIDE,
+                        M.KERNEL_HYBRID):
             for tile in (0, 11, 6, 3):
                 print(f"[autotune] variant={variant} tile={tile}", flush=True)
                 assert M.mortar_set_tuning(op.h, 0, variant, tile, 0) == 0
@@ -66,7 +67,7 @@ def test_single_interface_every_variant_and_tile(M):
         outs = H.gpu_flux(op, [spec], dins)
         assert _same(outs[0][0], per_variant[M.KERNEL_VALU][0])
         chosen = op.autotune(*_args(dins, H.gpu_flux(op, [spec], dins)), reps=2)
-        assert chosen[0]["variant"] in (0, 1, 2, 3)
+        assert chosen[0]["variant"] in (0, 1, 2, 3, 4)
         outs = H.gpu_flux(op, [spec], dins)
         err = H.rel_err(spec, (outs[0][0].cpu().numpy(), outs[0][1].cpu().numpy()), ref)
         assert np.max(err) <= H.TOL[W.FP32], (chosen, err)

@@ -21,10 +21,10 @@ def M():
 
 
 def _run_and_compare(M, spec, disps, seed=1, noise=1e-3, rows=None, check_maps=True,
-                     variant=None):
+                     variant=None, tile=0):
     op = M.MortarOperator([spec])
     if variant is not None:
-        assert M.mortar_set_tuning(op.h, 0, variant, 0, 0) == 0
+        assert M.mortar_set_tuning(op.h, 0, variant, tile, 0) == 0
     inp = W.make_inputs(spec, seed=seed, delta=disps[0], noise=noise)
     din, oin = H.device_inputs(spec, inp), H.oracle_inputs(spec, inp)
     worst = 0.0
@@ -192,8 +192,41 @@ def test_conservation_on_device(M, precision):
 
 
 # every launch variant the autotuner may pick: VALU, MFMA-LDS, register-direct, and
-# (FP32 only) wide-tile VALU
-_VARIANTS = {W.FP32: (0, 1, 2, 3), W.FP64: (0, 1, 2)}
+# (FP32 only) wide-tile VALU and matrix-core-projection hybrid
+_VARIANTS = {W.FP32: (0, 1, 2, 3, 4), W.FP64: (0, 1, 2)}
+
+
+@pytest.mark.parametrize("N,node_set,physics,riemann,annulus", [
+    (1, W.GAUSS, W.EULER, W.ROE, False), (2, W.LGL, W.NS, W.ROE, False),
+    (3, W.LGL, W.EULER, W.LF, True), (4, W.GAUSS, W.NS, W.LF, False),
+    (5, W.GAUSS, W.NS, W.ROE, True), (6, W.GAUSS, W.EULER, W.ROE, False),
+    (7, W.LGL, W.NS, W.ROE, True), (8, W.GAUSS, W.EULER, W.LF, True),
+    (9, W.GAUSS, W.EULER, W.ROE, False)])
+def test_hybrid_kernel_degrees(M, N, node_set, physics, riemann, annulus):
+    """The matrix-core-projection kernel (FP32) over degrees, node sets, fluxes and
+    per-point metrics: 37 faces per row (several tiles of 16-face chunks and a ragged
+    last one), scrambled columns, two tile lengths."""
+    if annulus:
+        spec = W.make_annulus(N, 37, 2, seed=N, physics=physics, riemann=riemann,
+                              node_set=node_set, mu=1e-3 if physics == W.NS else 0.0,
+                              precision=W.FP32, name="hyb-annulus")
+    else:
+        spec = W.make_plane(N, 37, 2, physics=physics, riemann=riemann, node_set=node_set,
+                            mu=1e-3 if physics == W.NS else 0.0, precision=W.FP32,
+                            scramble_seed=N, extra_cols=2, name="hyb")
+    for tile in (0, 7):
+        _run_and_compare(M, spec, [0.41 * spec.l_par, 9.73 * spec.l_par], seed=N, noise=1e-3,
+                         check_maps=False, variant=M.KERNEL_HYBRID, tile=tile)
+
+
+def test_hybrid_kernel_refuses_untileable(M):
+    """Degree 9 with Navier-Stokes gradients does not fit the hybrid kernel's LDS tile."""
+    spec = W.make_plane(9, 8, 1, physics=W.NS, riemann=W.ROE, mu=1e-3, precision=W.FP32)
+    op = M.MortarOperator([spec])
+    try:
+        assert M.mortar_set_tuning(op.h, 0, M.KERNEL_HYBRID, 0, 0) == -1
+    finally:
+        op.close()
 
 
 @pytest.mark.parametrize("precision,variant",
