@@ -43,6 +43,9 @@ def parse():
                    help="JSON file of earlier autotuner choices (read, and written on a miss)")
     p.add_argument("--precision", choices=("fp32", "bf16", "fp16"), default="fp32",
                    help="headline leg: FP32, or FP32 data with bf16 / fp16 projection GEMMs")
+    p.add_argument("--tuning", default=None,
+                   help="VARIANT,TILE,GRID: launch the headline leg with this tuning on every "
+                        "interface instead of autotuning it")
     p.add_argument("--copy-calibration", type=float, default=0.0,
                    help="only run a plain device copy of this many MB (counter calibration)")
     return p.parse_args()
@@ -64,34 +67,46 @@ def copy_calibration(mb):
 TRAFFIC_PROFILES = {2: "profiles/k_mortar_flux_ns_n5_plane128x64_traffic.md"}
 
 
+def sources_sha256(names):
+    import hashlib
+    h = hashlib.sha256()
+    for name in names:
+        with open(os.path.join(ROOT, "paper_2008_04356_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def measured_traffic(config, precision, tuning):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter
-    summary, or None when there is none for this workload, the kernel sources have
-    changed since the counters were taken, or the autotuner picked another launch."""
-    import hashlib
+    summary: its lines "launch variant=V tile_len=T grid=G traffic=BYTES sources=a,b,..
+    sha256=HEX" give the measured traffic of one launch each.  None when there is none for
+    this workload and launch, or the kernel sources have changed since the counters were
+    taken."""
     rel = TRAFFIC_PROFILES.get(config)
     if rel is None or precision != "fp32" or not tuning:
         return None
     path = os.path.join(ROOT, rel)
     if not os.path.exists(path):
         return None
-    kv = {}
     for line in open(path):
-        if ":" in line and not line.startswith((" ", "#", "-", "|")):
-            k, v = line.split(":", 1)
-            kv[k.strip()] = v.strip()
-    try:
-        h = hashlib.sha256()
-        for name in kv["sources"].split():
-            with open(os.path.join(ROOT, "paper_2008_04356_amd", "csrc", name), "rb") as fh:
-                h.update(fh.read())
-        t = dict(x.split("=") for x in kv["tuning"].split())
-        same_launch = all(int(t[k]) == tuning[0][k] for k in ("variant", "tile_len", "grid"))
-        if h.hexdigest() != kv["sources_sha256"] or not same_launch:
+        if not line.startswith("launch "):
+            continue
+        try:
+            kv = dict(x.split("=", 1) for x in line.split()[1:])
+            if any(int(kv[k]) != tuning[0][k] for k in ("variant", "tile_len", "grid")):
+                continue
+            if sources_sha256(kv["sources"].split(",")) != kv["sha256"]:
+                return None
+            return int(kv["traffic"])
+        except (KeyError, ValueError, OSError):
             return None
-        return int(kv["traffic_bytes_per_launch"])
-    except (KeyError, ValueError, OSError):
-        return None
+    return None
+
+
+# kernel (symbol name) of each launch variant
+KERNEL_OF_VARIANT = {0: "k_mortar_flux (VALU projections, 48 KB LDS)", 1: "k_mortar_flux_mfma",
+                     2: "k_mortar_flux_rd", 3: "k_mortar_flux (VALU projections, 72 KB LDS)",
+                     4: "k_mortar_flux_hyb"}
 
 
 def algorithmic_bytes(spec):
@@ -107,7 +122,7 @@ def algorithmic_bytes(spec):
 
 
 def run_leg(M, W, specs, disp, steps, warmup, rotate_bytes, graph=False, plain=False, tune=True,
-            tune_cache=None):
+            tune_cache=None, fixed=None):
     """Times one precision of a workload.  plain: one handle (one launch) per interface
     instead of the batched persistent launch; graph: each stage replays a captured HIP
     graph instead of eager launches; tune: the library's autotuner picks each launch
@@ -147,7 +162,14 @@ def run_leg(M, W, specs, disp, steps, warmup, rotate_bytes, graph=False, plain=F
                 [per[i]["Gm"] for i in sel], [per[i]["Fs"] for i in sel], [per[i]["Fm"] for i in sel])
 
     tuning = None
-    if tune:
+    if fixed is not None:
+        tuning = []
+        for i, op in enumerate(ops):
+            op.update([disp(0)[i]] if plain else disp(0))
+            op.set_tuning([dict(zip(("variant", "tile_len", "grid"), fixed))] * len(op.specs))
+            tuning += op.tuning()
+        print(f"[bench] fixed tuning: {tuning}", file=sys.stderr, flush=True)
+    elif tune:
         t1 = time.time()
         tuning = []
         for i, op in enumerate(ops):
@@ -196,20 +218,33 @@ def run_leg(M, W, specs, disp, steps, warmup, rotate_bytes, graph=False, plain=F
     cs = torch.cat(cons_dev).cpu().numpy()
     step_cons_rel = float(np.max(np.abs(cs[:, :, 0] - cs[:, :, 1]) / cs[:, :, 2]))
 
-    # the fused flux launch(es) alone, timed with HIP events on the stream they run on
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(steps)]
+    # the fused flux launch(es) alone, timed with HIP events on the stream they run on:
+    # the average over a region of back-to-back launches (per-launch event pairs add the
+    # events' own cost to every launch; they only give the spread)
     d = disp(warmup + steps)
     for i, op in enumerate(ops):
         op.update([d[i]] if plain else d)
-    for k in range(steps):
-        per = sets[k % nsets]
-        evs[k][0].record()
+
+    def flux_only(per):
         if plain:
             for i, op in enumerate(ops):
                 op.flux(*args(per, [i]))
         else:
             ops[0].flux(*args(per))
+
+    r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    r0.record()
+    for k in range(steps):
+        flux_only(sets[k % nsets])
+    r1.record()
+    torch.cuda.synchronize()
+    kavg = r0.elapsed_time(r1) / steps
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    for k in range(steps):
+        evs[k][0].record()
+        flux_only(sets[k % nsets])
         evs[k][1].record()
     torch.cuda.synchronize()
     kms = np.array([a.elapsed_time(b) for a, b in evs])
@@ -226,15 +261,14 @@ def run_leg(M, W, specs, disp, steps, warmup, rotate_bytes, graph=False, plain=F
     for op in ops:
         op.close()
     pts = sum(s.mortar_points for s in specs)
-    kavg = float(np.mean(kms))
     achieved = set_bytes / (kavg * 1e-3) / 1e9
     return {
         "pts_per_s": pts / (ms_step * 1e-3),
         "ms_per_step": ms_step,
         "kernel_ms_avg": kavg,
-        "kernel_ms_median": float(np.median(kms)),
-        "kernel_ms_min": float(np.min(kms)),
-        "kernel_ms_max": float(np.max(kms)),
+        "kernel_ms_median_event_pair": float(np.median(kms)),
+        "kernel_ms_min_event_pair": float(np.min(kms)),
+        "kernel_ms_max_event_pair": float(np.max(kms)),
         "kernel_pts_per_s": pts / (kavg * 1e-3),
         "bytes_per_launch": set_bytes,
         "achieved_GBs": achieved,
@@ -321,8 +355,9 @@ def main():
     torch.cuda.set_device(0)
     prec = {"fp32": W.FP32, "bf16": W.BF16_MFMA, "fp16": W.FP16_MFMA}[a.precision]
     specs32, disp = W.config(a.config, precision=prec)
+    fixed = None if a.tuning is None else tuple(int(x) for x in a.tuning.split(","))
     r32 = run_leg(M, W, specs32, disp, a.steps, a.warmup, a.rotate_bytes, graph=a.graph,
-                  tune=not a.no_autotune, tune_cache=a.tune_cache)
+                  tune=not a.no_autotune, tune_cache=a.tune_cache, fixed=fixed)
     r64 = None
     if not a.no_fp64:
         specs64, _ = W.config(a.config, precision=W.FP64)
@@ -332,9 +367,13 @@ def main():
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(M, W, specs32[0], disp, a.cpu_stages)
-    kname = {1: "k_mortar_flux<float,4,Euler,LF>", 2: "k_mortar_flux<float,6,NS,Roe>",
-             3: "k_mortar_flux<float,8,NS+metrics,Roe>", 4: "k_mortar_flux_batch<float,NS,Roe,N=3,5,7>",
-             5: "k_mortar_flux<float,10,Euler,Roe>"}
+    kargs = {1: "<float,4,Euler,LF>", 2: "<float,6,NS,Roe>", 3: "<float,8,NS+metrics,Roe>",
+             4: "<float,NS,Roe,N=3,5,7>", 5: "<float,10,Euler,Roe>"}
+    tuned = r32["tuning"][0]["variant"] if r32["tuning"] else 0
+    if len(specs32) > 1:
+        kernel = ("k_mortar_flux_rd_batch" if tuned == 2 else "k_mortar_flux_batch") + kargs[a.config]
+    else:
+        kernel = KERNEL_OF_VARIANT.get(tuned, "?") + " " + kargs.get(a.config, "")
     spec = specs32[0]
     names = {2: f"plane sliding interface N={spec.N}, {spec.n_par}x{spec.n_perp} face pairs, "
                 "Navier-Stokes Roe+BR1 (mu=1e-4), displacement 0.0137 l_par per stage, FP32",
@@ -367,15 +406,16 @@ def main():
                        "frac": r64["frac"],
                        "conservation_rel_residual": r64["conservation_rel_residual"],
                        "tuning": r64["tuning"]},
-                   "fp32_kernel": {k: r32[k] for k in ("kernel_ms_avg", "kernel_ms_median",
-                                                       "kernel_ms_min", "kernel_ms_max",
+                   "fp32_kernel": {k: r32[k] for k in ("kernel_ms_avg", "kernel_ms_median_event_pair",
+                                                       "kernel_ms_min_event_pair",
+                                                       "kernel_ms_max_event_pair",
                                                        "kernel_pts_per_s",
                                                        "conservation_rel_residual",
                                                        "rotated_sets", "tuning")}},
         "roofline": {"bound": "hbm", "achieved": r32["achieved_GBs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": r32["frac"],
                      "traffic": measured_traffic(a.config, a.precision, r32["tuning"]),
-                     "kernel": kname.get(a.config),
+                     "kernel": kernel,
                      "bytes_per_launch": r32["bytes_per_launch"]},
         "cpu_baseline": cpu,
     }
