@@ -21,9 +21,10 @@
  * Positions along the sliding direction are kept relative to a nearby integer face
  * boundary so that large face counts do not cost precision.
  *
- * Readings where the paper is silent or garbled are listed in the design notes of
- * the repository (node set, sub-interval naming, Roe/Harten-Hyman details, BR1
- * gradients of conservative variables, no grid-velocity term on a sliding interface).
+ * Where the paper is silent or garbled this code takes one reading each: the node set
+ * is a parameter, the sub-intervals are named by their position on the face, the Roe
+ * solver carries the Harten-Hyman fix on the acoustic fields only, BR1 uses gradients
+ * of the conservative variables, and a sliding interface has no grid-velocity term.
  *
  * Compiled with -ffp-contract=off: every product and sum is rounded as written.
  */

@@ -79,7 +79,29 @@ struct FluxArgs {
     int n_tiles;                  // tiles_per_row * NP * n_perp
     T nx, ny, nz, dS;
     GasConsts<T> gas;
+    // conservation partials of this launch, or null: the workgroup's FP64 sums of
+    // w_p w_q F and w_p w_q |F| per (variable, side) group g = 2 v + side at
+    // cons[(g * gridDim.x + blockIdx.x) * 2 + {0, 1}]
+    double *cons;
 };
+
+// Compensated (Neumaier) FP64 sum.
+struct ConsSum {
+    double s = 0.0, c = 0.0;
+    __device__ __forceinline__ void add(double x)
+    {
+        const double t = s + x;
+        c += (fabs(s) >= fabs(x)) ? (s - t) + x : (x - t) + s;
+        s = t;
+    }
+    __device__ __forceinline__ double value() const { return s + c; }
+};
+
+// Zero conservation partials of a workgroup that had no tile of the interface.
+__device__ __forceinline__ void cons_zero(double *cons)
+{
+    if (cons && threadIdx.x < 20) cons[((size_t)(threadIdx.x >> 1) * gridDim.x + blockIdx.x) * 2 + (threadIdx.x & 1)] = 0.0;
+}
 
 constexpr int kFluxThreads = 256;
 constexpr int kHalf = kFluxThreads / 2;
@@ -329,7 +351,7 @@ constexpr size_t flux_smem_bytes()
 // All tiles of one interface that this workgroup's cursor visits (the cursor is valid
 // on entry).  smem holds flux_smem_bytes() bytes, 16-aligned.  Ends with a barrier, so
 // the caller may reuse smem at once.
-template <typename T, int NP, bool NSV, bool MET, int RIEM, int BUDGET>
+template <typename T, int NP, bool NSV, bool MET, int RIEM, int BUDGET, bool CONS = true>
 __device__ __forceinline__ void run_interface(const FluxArgs<T> &a, TileCursor &cur, char *smem)
 {
     using C = FluxCfg<T, NP, NSV, MET, BUDGET>;
@@ -349,6 +371,13 @@ __device__ __forceinline__ void run_interface(const FluxArgs<T> &a, TileCursor &
     const int np_ = a.n_par;
     const int nmod = a.nmod;
     const size_t plane_s = (size_t)P * a.nfs, plane_m = (size_t)P * a.nfm;
+
+    // conservation sums of this thread's back-projection items (item k3 always has the
+    // same variable), over all its tiles
+    // (a plain sum: a thread adds one value per tile)
+    double csum[C::ITEMS3], cmag[C::ITEMS3];
+#pragma unroll
+    for (int k = 0; k < C::ITEMS3; ++k) csum[k] = cmag[k] = 0.0;
 
     // Pipeline: the face lines of tile t+1 are loaded while tile t is processed; at the
     // start of tile t the input columns of tile t+2 and the output columns of tile t+1
@@ -461,6 +490,7 @@ __device__ __forceinline__ void run_interface(const FluxArgs<T> &a, TileCursor &
                 // every lane stores; a dead item's offset lies beyond the array
                 const bool ok = e < 5 * TF && f < g.nf;
                 const uint32_t o0 = ((uint32_t)(v * NN + NP * g.pp) * nfo + (uint32_t)col3[k3]) * (uint32_t)sizeof(T);
+                double ls = 0.0, lm = 0.0;       // this face line's w_j-weighted sums
 #pragma unroll
                 for (int j = 0; j < NP; ++j) {
                     T acc = T(0);
@@ -470,6 +500,14 @@ __device__ __forceinline__ void run_interface(const FluxArgs<T> &a, TileCursor &
                         acc += B_hi[j * NP + q] * hi[q];
                     }
                     buf_store<T>(acc, rF, ok ? o0 + (uint32_t)(j * sizeof(T)) * nfo : kBufOff, 0);
+                    const double y = a.basis->w[j] * (double)acc;
+                    ls += y;
+                    lm += fabs(y);
+                }
+                if (CONS && a.cons && ok) {
+                    const double wl = a.basis->w[g.pp];
+                    csum[k3] += wl * ls;
+                    cmag[k3] += wl * lm;
                 }
             }
         }
@@ -483,6 +521,38 @@ __device__ __forceinline__ void run_interface(const FluxArgs<T> &a, TileCursor &
 #pragma unroll
         for (int k = 0; k < C::ITEMS3; ++k) col3[k] = col3_n[k];
     }
+
+    // conservation partials: per (variable, side) group, one side at a time, thread v
+    // adds the side's items e = v TF .. v TF + TF - 1 (thread e % 128, item e / 128) in a
+    // fixed order
+    if (CONS && a.cons) {
+        static_assert(C::LDS_T * sizeof(T) >= (size_t)kHalf * C::ITEMS3 * 2 * sizeof(double),
+                      "conservation staging");
+        double *red = reinterpret_cast<double *>(smem);
+        for (int sd = 0; sd < 2; ++sd) {
+            if (side == sd) {
+#pragma unroll
+                for (int k = 0; k < C::ITEMS3; ++k) {
+                    red[(lt * C::ITEMS3 + k) * 2 + 0] = csum[k];
+                    red[(lt * C::ITEMS3 + k) * 2 + 1] = cmag[k];
+                }
+            }
+            __syncthreads();
+            if (tid < 5) {
+                ConsSum t;
+                double m = 0.0;
+                for (int e = tid * TF; e < (tid + 1) * TF; ++e) {
+                    const double *r = red + ((e % kHalf) * C::ITEMS3 + e / kHalf) * 2;
+                    t.add(r[0]);
+                    m += r[1];
+                }
+                const size_t o = ((size_t)(2 * tid + sd) * gridDim.x + blockIdx.x) * 2;
+                a.cons[o + 0] = t.value();
+                a.cons[o + 1] = m;
+            }
+            __syncthreads();
+        }
+    }
 }
 
 template <typename T, int NP, bool NSV, bool MET, int RIEM, int BUDGET>
@@ -490,7 +560,10 @@ __global__ __launch_bounds__(kFluxThreads) void k_mortar_flux(FluxArgs<T> a)
 {
     __shared__ __attribute__((aligned(16))) char smem[flux_smem_bytes<T, NP, NSV, MET, BUDGET>()];
     TileCursor cur(a.n_tiles);
-    if (!cur.valid()) return;               // uniform over the workgroup
+    if (!cur.valid()) {                     // uniform over the workgroup
+        cons_zero(a.cons);
+        return;
+    }
     run_interface<T, NP, NSV, MET, RIEM, BUDGET>(a, cur, smem);
 }
 
@@ -546,7 +619,7 @@ template <typename T, int NP, bool NSV, bool MET, int RIEM, int BUDGET>
 __device__ __noinline__ void run_interface_call(const FluxArgs<T> *a, char *smem)
 {
     TileCursor cur(a->n_tiles);
-    run_interface<T, NP, NSV, MET, RIEM, BUDGET>(*a, cur, smem);
+    run_interface<T, NP, NSV, MET, RIEM, BUDGET, false>(*a, cur, smem);
 }
 
 template <typename T, int NP, bool NSV, bool MET, int RIEM, int BUDGET, bool CALL>
@@ -556,7 +629,7 @@ __device__ __forceinline__ void run_batch_member(const FluxArgs<T> *a, char *sme
         run_interface_call<T, NP, NSV, MET, RIEM, BUDGET>(a, smem);
     } else {
         TileCursor cur(a->n_tiles);
-        run_interface<T, NP, NSV, MET, RIEM, BUDGET>(*a, cur, smem);
+        run_interface<T, NP, NSV, MET, RIEM, BUDGET, false>(*a, cur, smem);
     }
 }
 

@@ -304,6 +304,13 @@ static int cons_face_blocks(int nfaces) { return std::max(1, std::min(256, (nfac
 // Partials per (variable, side) group.
 int cons_blocks(int P, int nfaces) { return cons_face_blocks(nfaces) * ((P + 7) / 8); }
 
+// Sums from the partials a fused flux launch wrote (one per workgroup and group).
+hipError_t launch_conservation_final(const Iface &f, double *d_out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cons_final, dim3(1), dim3(640), 0, st, f.d_cons_wg, f.cons_nb, d_out);
+    return hipGetLastError();
+}
+
 hipError_t launch_conservation(const Iface &f, const void *Fs, const void *Fm, double *d_out,
                                hipStream_t st)
 {

@@ -284,7 +284,7 @@ static void free_iface(Iface &f)
 {
     void *bufs[] = {f.d_fid_s, f.d_fid_m, f.d_oid_s, f.d_oid_m, f.d_oval_s, f.d_oval_m,
                     f.d_metrics, f.d_params, f.d_basis, f.d_A[0], f.d_A[1], f.d_m[0],
-                    f.d_m[1], f.d_hist, f.d_cons, f.d_cons_out};
+                    f.d_m[1], f.d_hist, f.d_cons, f.d_cons_out, f.d_cons_wg};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     f = Iface();
@@ -415,10 +415,12 @@ static int setup_one(const mortar_iface_desc &d, Iface &f)
     if (hipMalloc((void **)&f.d_cons_out, sizeof(double) * 15) != hipSuccess) return MORTAR_ERR_OOM;
     if (hipMalloc((void **)&f.d_cons, sizeof(double) * 40 * (size_t)f.n_cons_blocks) != hipSuccess)
         return MORTAR_ERR_OOM;
+    if (hipMalloc((void **)&f.d_cons_wg, sizeof(double) * 20 * (size_t)kConsGridMax) != hipSuccess)
+        return MORTAR_ERR_OOM;
     return MORTAR_OK;
 }
 
-// R6 of the design notes: FP64, no contraction, s in [0, 1).
+// Displacement split (Sec. 4.3): n = floor(delta / l), s = the rest in [0, 1), in FP64.
 static void decompose(double delta, double l, int64_t &n, double &s)
 {
     const double q = delta / l;
@@ -432,6 +434,16 @@ static void decompose(double delta, double l, int64_t &n, double &s)
     if (!(frac > 0.0)) frac = 0.0;
     n = k;
     s = frac;
+}
+
+// Conservation sums of a face-flux pair: from the partials of the fused flux launch
+// when these are its outputs (the sums of exactly the values it wrote), else by a pass
+// over the arrays.
+static hipError_t launch_conservation_any(const Iface &f, const void *Fs, const void *Fm, double *d_out,
+                                          hipStream_t st)
+{
+    if (f.cons_nb > 0 && f.cons_Fs == Fs && f.cons_Fm == Fm) return launch_conservation_final(f, d_out, st);
+    return launch_conservation(f, Fs, Fm, d_out, st);
 }
 
 static int apply_update(Handle *h, const int64_t *n, const double *s, hipStream_t st)
@@ -458,6 +470,9 @@ namespace mortar {
 template <typename T>
 void fill_args(const Iface &f, const void *Us, const void *Um, const void *Gs, const void *Gm,
                void *Fs, void *Fm, FluxArgs<T> &a, int &n_tiles);
+static int tiled_grid(const Iface &f, int n_cu, int nt);
+template <typename T>
+static void set_cons(const Iface &f, FluxArgs<T> &a, int grid, const void *Fs, const void *Fm);
 }  // namespace mortar
 
 using namespace mortar;
@@ -674,7 +689,7 @@ int mortar_conservation_device(mortar_handle *h, const void *const *F_s, const v
     for (size_t i = 0; i < h->ifs.size(); ++i)
         if (!F_s[i] || !F_m[i]) return MORTAR_ERR_INVALID_ARG;
     for (size_t i = 0; i < h->ifs.size(); ++i)
-        TRY_HIP(launch_conservation(h->ifs[i], F_s[i], F_m[i], d_out + 15 * i, (hipStream_t)stream));
+        TRY_HIP(launch_conservation_any(h->ifs[i], F_s[i], F_m[i], d_out + 15 * i, (hipStream_t)stream));
     return MORTAR_OK;
 }
 
@@ -686,7 +701,7 @@ int mortar_conservation(mortar_handle *h, const void *const *F_s, const void *co
     for (size_t i = 0; i < h->ifs.size(); ++i) {
         if (!F_s[i] || !F_m[i]) return MORTAR_ERR_INVALID_ARG;
         const Iface &f = h->ifs[i];
-        TRY_HIP(launch_conservation(f, F_s[i], F_m[i], f.d_cons_out, st));
+        TRY_HIP(launch_conservation_any(f, F_s[i], F_m[i], f.d_cons_out, st));
         TRY_HIP(hipMemcpyAsync(out + 15 * i, f.d_cons_out, sizeof(double) * 15,
                                hipMemcpyDeviceToHost, st));
     }
@@ -784,6 +799,7 @@ int mortar_graph_launch(mortar_graph *g, const double *disp, void *stream)
                 int nt = 0;
                 fill_args(h->ifs[i], g->Us[i], g->Um[i], g->Gs[i], g->Gm[i], g->Fs[i], g->Fm[i],
                           b.a[i], nt);
+                h->ifs[i].cons_nb = 0;
                 b.np[i] = h->ifs[i].NP;
                 b.met[i] = h->ifs[i].d_metrics != nullptr;
             }
@@ -803,10 +819,16 @@ int mortar_graph_launch(mortar_graph *g, const double *disp, void *stream)
             if (h->ifs[i].elem == 8) {
                 FluxArgs<double> a;
                 fill_args(h->ifs[i], g->Us[i], g->Um[i], g->Gs[i], g->Gm[i], g->Fs[i], g->Fm[i], a, nt);
+                h->ifs[i].cons_nb = 0;
+                if (h->ifs[i].flux_variant != 2)
+                    set_cons(h->ifs[i], a, tiled_grid(h->ifs[i], h->n_cu, nt), g->Fs[i], g->Fm[i]);
                 rc = set_node_args(g, i, a);
             } else {
                 FluxArgs<float> a;
                 fill_args(h->ifs[i], g->Us[i], g->Um[i], g->Gs[i], g->Gm[i], g->Fs[i], g->Fm[i], a, nt);
+                h->ifs[i].cons_nb = 0;
+                if (h->ifs[i].flux_variant != 2)
+                    set_cons(h->ifs[i], a, tiled_grid(h->ifs[i], h->n_cu, nt), g->Fs[i], g->Fm[i]);
                 rc = set_node_args(g, i, a);
             }
         }
@@ -821,19 +843,47 @@ int mortar_graph_launch(mortar_graph *g, const double *disp, void *stream)
 }  // extern "C"
 
 // Average time of one launch (ms): one warm-up, then reps launches between two events.
+// Device buffer larger than the caches (4 MB L2 per XCD, the 256 MB Infinity Cache),
+// filled before every timed call so that each starts with its inputs in HBM, as a stage
+// with fresh data does; released when the autotuner returns.
+struct CacheFlush {
+    static constexpr size_t kBytes = (size_t)512 << 20;
+    void *buf = nullptr;
+    CacheFlush()
+    {
+        if (hipMalloc(&buf, kBytes) != hipSuccess) buf = nullptr;   // then timed warm
+    }
+    ~CacheFlush()
+    {
+        if (buf) (void)hipFree(buf);
+    }
+    hipError_t run(int r, hipStream_t st) const
+    {
+        return buf ? hipMemsetAsync(buf, r & 0xff, kBytes, st) : hipSuccess;
+    }
+};
+
+// Average time of one call of launch() over reps timed calls (each between its own pair
+// of events, after a cache flush), following one untimed call.
 template <typename F>
-static hipError_t time_launches(F &&launch, int reps, hipStream_t st, float &ms)
+static hipError_t time_launches(F &&launch, int reps, hipStream_t st, float &ms, const CacheFlush &cf)
 {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t err = hipEventCreate(&e0);
     if (err == hipSuccess) err = hipEventCreate(&e1);
     if (err == hipSuccess) err = launch();
-    if (err == hipSuccess) err = hipEventRecord(e0, st);
-    for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch();
-    if (err == hipSuccess) err = hipEventRecord(e1, st);
-    if (err == hipSuccess) err = hipEventSynchronize(e1);
-    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-    if (err == hipSuccess) ms /= (float)reps;
+    float total = 0.f;
+    for (int r = 0; r < reps && err == hipSuccess; ++r) {
+        err = cf.run(r, st);
+        if (err == hipSuccess) err = hipEventRecord(e0, st);
+        if (err == hipSuccess) err = launch();
+        if (err == hipSuccess) err = hipEventRecord(e1, st);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+        total += t;
+    }
+    ms = total / (float)reps;
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     return err;
@@ -875,6 +925,7 @@ int mortar_autotune(mortar_handle *h, const void *const *U_s, const void *const 
         if (ns && (!G_s || !G_m || !G_s[i] || !G_m[i])) return MORTAR_ERR_INVALID_ARG;
     }
     h->tune_epoch++;
+    const CacheFlush flush;
     float ms = 0.f;
     // MORTAR_TUNE_LOG=1 prints every candidate's time to stderr
     const bool log = std::getenv("MORTAR_TUNE_LOG") != nullptr;
@@ -907,7 +958,7 @@ int mortar_autotune(mortar_handle *h, const void *const *U_s, const void *const 
                 float bi = 1e30f;
                 for (int t : tile_candidates(vmax_tile(f, v))) {
                     f.tune_tile = t;
-                    TRY_HIP(time_launches(run, reps, st, ms));
+                    TRY_HIP(time_launches(run, reps, st, ms, flush));
                     note((int)i, v, t, h->tune_grid_batch);
                     if (ms < bi) { bi = ms; best_t = t; }
                 }
@@ -918,7 +969,7 @@ int mortar_autotune(mortar_handle *h, const void *const *U_s, const void *const 
             float bg = 1e30f;
             for (int k = occ; k >= 1; --k) {
                 h->tune_grid_batch = k == occ ? 0 : k * h->n_cu;
-                TRY_HIP(time_launches(run, reps, st, ms));
+                TRY_HIP(time_launches(run, reps, st, ms, flush));
                 note(-1, v, 0, h->tune_grid_batch);
                 if (ms < bg) { bg = ms; best_g = h->tune_grid_batch; }
             }
@@ -938,9 +989,13 @@ int mortar_autotune(mortar_handle *h, const void *const *U_s, const void *const 
     for (size_t i = 0; i < n_if; ++i) {
         Iface &f = h->ifs[i];
         const bool ns = f.d.physics == MORTAR_NAVIER_STOKES;
+        // a candidate's time includes the stage's conservation sums: fused into the VALU
+        // kernels' launch, a separate pass after the others
         auto run = [&]() {
-            return launch_flux(f, h->n_cu, U_s[i], U_m[i], ns ? G_s[i] : nullptr,
-                               ns ? G_m[i] : nullptr, F_s[i], F_m[i], st);
+            hipError_t e = launch_flux(f, h->n_cu, U_s[i], U_m[i], ns ? G_s[i] : nullptr,
+                                       ns ? G_m[i] : nullptr, F_s[i], F_m[i], st);
+            if (e == hipSuccess) e = launch_conservation_any(f, F_s[i], F_m[i], f.d_cons_out, st);
+            return e;
         };
         int best_v = f.flux_variant, best_t = f.tune_tile;
         float best = 1e30f;
@@ -951,7 +1006,7 @@ int mortar_autotune(mortar_handle *h, const void *const *U_s, const void *const 
             f.tune_grid = 0;
             for (int t : tile_candidates(vmax_tile(f, v))) {
                 f.tune_tile = t;
-                TRY_HIP(time_launches(run, reps, st, ms));
+                TRY_HIP(time_launches(run, reps, st, ms, flush));
                 note((int)i, v, t, 0);
                 if (ms < best) { best = ms; best_v = v; best_t = t; }
             }
@@ -1049,6 +1104,27 @@ void fill_args(const Iface &f, const void *Us, const void *Um, const void *Gs,
     a.nx = (T)f.d.normal[0]; a.ny = (T)f.d.normal[1]; a.nz = (T)f.d.normal[2];
     a.dS = (T)f.d.dS;
     a.gas = {(T)gm1, (T)f.d.gamma, (T)(ns ? f.d.mu : 0.0), (T)kfac};
+    a.cons = nullptr;
+}
+
+// Persistent grid of the LDS-tiled kernels: at least min(8, n_tiles) workgroups so that
+// every XCD's share of the tiles has workers (TileCursor).
+static int tiled_grid(const Iface &f, int n_cu, int nt)
+{
+    if (f.tune_grid > 0) return std::max(std::min(8, nt), std::min(nt, f.tune_grid));
+    return std::max(1, std::min(nt, f.flux_occ * n_cu));
+}
+
+// The VALU-projection kernels (variants 0 and 3) also write the conservation partials of
+// their launch; record which outputs they belong to.
+template <typename T>
+static void set_cons(const Iface &f, FluxArgs<T> &a, int grid, const void *Fs, const void *Fm)
+{
+    const bool fused = (f.flux_variant == 0 || f.flux_variant == 3) && grid <= kConsGridMax;
+    a.cons = fused ? f.d_cons_wg : nullptr;
+    f.cons_Fs = fused ? Fs : nullptr;
+    f.cons_Fm = fused ? Fm : nullptr;
+    f.cons_nb = fused ? grid : 0;
 }
 
 hipError_t launch_flux(const Iface &f, int n_cu, const void *Us, const void *Um, const void *Gs,
@@ -1058,6 +1134,7 @@ hipError_t launch_flux(const Iface &f, int n_cu, const void *Us, const void *Um,
     const bool met = f.d_metrics != nullptr;
     const int riem = f.d.riemann == MORTAR_FLUX_ROE ? 1 : 0;
     int n_tiles = 0;
+    f.cons_nb = 0;
     if (f.flux_variant == 2) {
         // one tile per wave, four waves per workgroup; at least one workgroup per XCD
         auto rd_grid = [&](int nt) {
@@ -1076,22 +1153,18 @@ hipError_t launch_flux(const Iface &f, int n_cu, const void *Us, const void *Um,
         if (f.lp == 2) return launch_flux_rd_fp16(a, f.NP, grid, ns, met, riem, st);
         return launch_flux_rd_f32(a, f.NP, grid, ns, met, riem, st);
     }
-    // persistent grid: at least min(8, n_tiles) workgroups so that every XCD's share of
-    // the tiles has workers (TileCursor)
-    auto grid_of = [&](int nt) {
-        if (f.tune_grid > 0) return std::max(std::min(8, nt), std::min(nt, f.tune_grid));
-        return std::max(1, std::min(nt, f.flux_occ * n_cu));
-    };
     if (f.elem == 8) {
         FluxArgs<double> a;
         fill_args(f, Us, Um, Gs, Gm, Fs, Fm, a, n_tiles);
-        const int grid = grid_of(n_tiles);
+        const int grid = tiled_grid(f, n_cu, n_tiles);
+        set_cons(f, a, grid, Fs, Fm);
         return f.flux_variant == 1 ? launch_flux_mfma_f64(a, f.NP, grid, ns, met, riem, st)
                                    : launch_flux_f64(a, f.NP, grid, ns, met, riem, st);
     }
     FluxArgs<float> a;
     fill_args(f, Us, Um, Gs, Gm, Fs, Fm, a, n_tiles);
-    const int grid = grid_of(n_tiles);
+    const int grid = tiled_grid(f, n_cu, n_tiles);
+    set_cons(f, a, grid, Fs, Fm);
     if (f.flux_variant == 3) return launch_flux_wide_f32(a, f.NP, grid, ns, met, riem, st);
     if (f.flux_variant == 4) return launch_flux_hyb_f32(a, f.NP, grid, ns, met, riem, st);
     return f.flux_variant == 1 ? launch_flux_mfma_f32(a, f.NP, grid, ns, met, riem, st)
@@ -1113,6 +1186,7 @@ hipError_t launch_flux_batched(const Handle &h, const void *const *Us, const voi
             int nt = 0;
             fill_args(f, Us[i], Um[i], ns ? Gs[i] : nullptr, ns ? Gm[i] : nullptr, Fs[i], Fm[i],
                       b.a[i], nt);
+            f.cons_nb = 0;                       // the batched kernels write no partials
             b.np[i] = f.NP;
             b.met[i] = f.d_metrics != nullptr;
             total += nt;

@@ -68,6 +68,10 @@ struct Iface {
     int64_t nmod_built = -1;           // n mod n_par of the current index map
     bool ready = false;
     double *d_cons = nullptr;          // conservation partials [10][blocks][4]
+    double *d_cons_wg = nullptr;       // partials of the fused flux launch [10][kConsGridMax][2]
+    // the flux launch whose fused partials d_cons_wg holds: output arrays and grid (0: none)
+    mutable const void *cons_Fs = nullptr, *cons_Fm = nullptr;
+    mutable int cons_nb = 0;
     double *d_cons_out = nullptr;      // conservation sums [5][3] of the last host query
     int n_cons_blocks = 0;
     int flux_occ = 1;                  // resident flux workgroups per CU
@@ -102,6 +106,9 @@ hipError_t launch_flux_batched(const Handle &h, const void *const *Us, const voi
                                const void *const *Gs, const void *const *Gm, void *const *Fs,
                                void *const *Fm, hipStream_t st);
 int cons_blocks(int P, int nfaces);
+// Largest flux grid whose workgroups write conservation partials.
+constexpr int kConsGridMax = 4096;
+hipError_t launch_conservation_final(const Iface &f, double *d_out, hipStream_t st);
 hipError_t launch_conservation(const Iface &f, const void *Fs, const void *Fm, double *d_out,
                                hipStream_t st);
 
