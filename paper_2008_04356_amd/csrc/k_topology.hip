@@ -207,11 +207,11 @@ __device__ __forceinline__ double cons_wave_add(double x)
     return x;
 }
 
-// Partial sums: block (bx, by, g) with g = v * 2 + side sums w_p w_q F and w_p w_q |F|
-// of variable v on one side over the faces f = bx*256 + t + j*gridDim.x*256 and the
-// points p = 8 by .. 8 by + 7 (consecutive threads read consecutive face columns).
-// Each thread accumulates with compensation; the few levels that combine threads and
-// blocks add plain doubles in fixed orders.  part[(g * gridDim.y + by) * gridDim.x + bx][2].
+// Partial sums: block (bx, g) with g = v * 2 + side sums w_p w_q F and w_p w_q |F| of
+// variable v on one side over the faces f = bx*256 + t + j*gridDim.x*256 and all points
+// of each (consecutive threads read consecutive face columns, eight points in flight per
+// thread).  Each thread accumulates with compensation; the few levels that combine
+// threads and blocks add plain doubles in fixed orders.  part[(g * gridDim.x + bx)][2].
 template <typename T>
 __global__ __launch_bounds__(256) void k_cons_partial(const T *__restrict__ Fs,
                                                       const T *__restrict__ Fm,
@@ -223,31 +223,30 @@ __global__ __launch_bounds__(256) void k_cons_partial(const T *__restrict__ Fs,
 {
     constexpr int PG = 8;
     __shared__ double red[4][2];
+    __shared__ double wpq[kMaxNP * kMaxNP + PG];   // w_p w_q of point p, 0 past the last
     const int P = NP * NP;
-    const int g = blockIdx.z, v = g >> 1, side = g & 1;
+    for (int p = threadIdx.x; p < P + PG; p += blockDim.x)
+        wpq[p] = p < P ? basis->w[p % NP] * basis->w[p / NP] : 0.0;
+    __syncthreads();
+    const int g = blockIdx.y, v = g >> 1, side = g & 1;
     const int nf = side ? nfm : nfs;
     const T *F = (side ? Fm : Fs) + (size_t)v * P * nf;
     const int32_t *fid = side ? fid_m : fid_s;
-    const int p0 = PG * blockIdx.y;
-    double w[PG];
-#pragma unroll
-    for (int u = 0; u < PG; ++u) {
-        const int p = p0 + u;
-        w[u] = p < P ? basis->w[p % NP] * basis->w[p / NP] : 0.0;
-    }
     Neumaier sum, mag;
     for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < nfaces; f += gridDim.x * blockDim.x) {
         const T *col = F + fid[f];
-        T x[PG];
-        // unconditional loads (a point past P rereads the last one, with weight 0), so
-        // all of them are in flight at once
+        for (int p0 = 0; p0 < P; p0 += PG) {
+            T x[PG];
+            // unconditional loads (a point past P rereads the last one, with weight 0), so
+            // all of them are in flight at once
 #pragma unroll
-        for (int u = 0; u < PG; ++u) x[u] = col[(size_t)min(p0 + u, P - 1) * nf];
+            for (int u = 0; u < PG; ++u) x[u] = col[(size_t)min(p0 + u, P - 1) * nf];
 #pragma unroll
-        for (int u = 0; u < PG; ++u) {
-            const double y = w[u] * (double)x[u];
-            sum.add(y);
-            mag.add(fabs(y));
+            for (int u = 0; u < PG; ++u) {
+                const double y = wpq[p0 + u] * (double)x[u];
+                sum.add(y);
+                mag.add(fabs(y));
+            }
         }
     }
     const double s1 = cons_wave_add(sum.s + sum.c), s2 = cons_wave_add(mag.s + mag.c);
@@ -263,7 +262,7 @@ __global__ __launch_bounds__(256) void k_cons_partial(const T *__restrict__ Fs,
             a += red[w2][0];
             m += red[w2][1];
         }
-        double *o = part + (((size_t)g * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * 2;
+        double *o = part + ((size_t)g * gridDim.x + blockIdx.x) * 2;
         o[0] = a;
         o[1] = m;
     }
@@ -296,13 +295,16 @@ __global__ __launch_bounds__(640) void k_cons_final(const double *__restrict__ p
     }
 }
 
-// Conservation grid: blocks along the faces (one face per thread, at most 256 blocks;
-// larger interfaces loop) and point groups of eight.  The pass is latency-bound (face
-// column, then its values), so one face per thread keeps the chain short.
-static int cons_face_blocks(int nfaces) { return std::max(1, std::min(256, (nfaces + 255) / 256)); }
+// Conservation grid: blocks along the faces (one face per thread, every point of it;
+// at most 1024 blocks, larger interfaces loop) for each of the 10 (variable, side) groups.
+static int cons_face_blocks(int nfaces) { return std::max(1, std::min(1024, (nfaces + 255) / 256)); }
 
 // Partials per (variable, side) group.
-int cons_blocks(int P, int nfaces) { return cons_face_blocks(nfaces) * ((P + 7) / 8); }
+int cons_blocks(int P, int nfaces)
+{
+    (void)P;
+    return cons_face_blocks(nfaces);
+}
 
 // Sums from the partials a fused flux launch wrote (one per workgroup and group).
 hipError_t launch_conservation_final(const Iface &f, double *d_out, hipStream_t st)
@@ -314,8 +316,8 @@ hipError_t launch_conservation_final(const Iface &f, double *d_out, hipStream_t 
 hipError_t launch_conservation(const Iface &f, const void *Fs, const void *Fm, double *d_out,
                                hipStream_t st)
 {
-    const dim3 grid(cons_face_blocks(f.F), (f.P + 7) / 8, 10);
-    const int nb = (int)(grid.x * grid.y);
+    const dim3 grid(cons_face_blocks(f.F), 10);
+    const int nb = (int)grid.x;
     if (f.d.precision == MORTAR_FP64)
         hipLaunchKernelGGL(k_cons_partial<double>, grid, dim3(256), 0, st,
                            (const double *)Fs, (const double *)Fm, f.d_fid_s, f.d_fid_m,
