@@ -208,7 +208,10 @@ int mortar_get_projection(mortar_handle *h, int iface, double *Pf, double *Pb);
 
 /* Conservation sums in FP64 (compensated): out (host [n_iface][5][3]) gets, per variable,
  * the static-side integral sum w_p w_q F, the moving-side one and the sum of |terms|.
- * Reads the given flux arrays (device) on stream and synchronizes it. */
+ * When F_s/F_m are the outputs of the interface's last flux launch and that launch used
+ * a VALU-projection kernel, the sums come from the per-workgroup partials it wrote (the
+ * sums of exactly the values it stored); otherwise the flux arrays (device) are read.
+ * Runs on stream and synchronizes it. */
 int mortar_conservation(mortar_handle *h, const void *const *F_s, const void *const *F_m,
                         double *out, void *stream);
 
