@@ -152,15 +152,16 @@ __device__ __forceinline__ void viscous_flux(const T *U, const T *G, T nx, T ny,
         const T dp = g.gm1 * (Gd[4] - (v0 * Gd[1] + v1 * Gd[2] + v2 * Gd[3]) + half_v2 * Gd[0]);
         kgT[d] = g.kfac * (dp - p_over_r * Gd[0]) * ir;
     }
-    const T lam_div = T(-2.0 / 3.0) * g.mu * (gv[0][0] + gv[1][1] + gv[2][2]);
+    // traction tau n = mu ((grad v + grad v^T) n - 2/3 (div v) n), mu factored out
+    const T div23 = T(-2.0 / 3.0) * (gv[0][0] + gv[1][1] + gv[2][2]);
     const T nn[3] = {nx, ny, nz};
     T tn[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        T a = lam_div * nn[i];
+        T a = div23 * nn[i];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) a += g.mu * (gv[i][j] + gv[j][i]) * nn[j];
-        tn[i] = a;
+        for (int j = 0; j < 3; ++j) a += (gv[i][j] + gv[j][i]) * nn[j];
+        tn[i] = g.mu * a;
     }
     Fv[0] = T(0);
     Fv[1] = tn[0];

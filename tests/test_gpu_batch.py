@@ -120,3 +120,40 @@ def test_mixed_precisions_fall_back_to_separate_launches(M):
         torch.cuda.synchronize()
     finally:
         op.close()
+
+
+def test_graph_replay_conservation_from_fused_partials(M):
+    """A captured single-interface VALU launch writes its conservation partials on every
+    replay: the sums after each replay equal a pass over copies of the flux arrays, with
+    an eager launch into other buffers (and its partials) between the replays."""
+    import torch
+    spec = W.make_plane(5, 53, 3, physics=W.NS, riemann=W.ROE, mu=1e-3, precision=W.FP32,
+                        scramble_seed=5, extra_cols=1)
+    din = H.device_inputs(spec, W.make_inputs(spec, seed=31, noise=1e-2))
+    op = M.MortarOperator([spec])
+    try:
+        assert M.mortar_set_tuning(op.h, 0, M.KERNEL_VALU, 0, 0) == 0
+        outs = [H.alloc_outputs(spec, fill=0.0)]
+        other = [H.alloc_outputs(spec, fill=0.0)]
+        op.update([0.0])
+        graph = op.graph([din["Us"]], [din["Um"]], [din["Gs"]], [din["Gm"]],
+                         [outs[0][0]], [outs[0][1]])
+        try:
+            for k in range(4):
+                print(f"[graph] conservation stage {k}", flush=True)
+                graph.launch([(0.31 + 7.7 * k) * spec.l_par])
+                dev = torch.zeros((1, 5, 3), dtype=torch.float64, device="cuda:0")
+                op.conservation_device([outs[0][0]], [outs[0][1]], dev)
+                torch.cuda.synchronize()
+                fused = dev.cpu().numpy()[0]
+                passed = op.conservation([outs[0][0].clone()], [outs[0][1].clone()])[0]
+                assert np.all(np.abs(fused - passed) <= 1e-13 * passed[:, 2:3] + 1e-300), (k, fused, passed)
+                # an eager launch into other buffers moves the partials to those buffers
+                op.update([(0.77 + 3.1 * k) * spec.l_par])
+                H.gpu_flux(op, [spec], [din], outs=other)
+                again = op.conservation([outs[0][0]], [outs[0][1]])[0]
+                assert np.all(np.abs(again - passed) <= 1e-13 * passed[:, 2:3] + 1e-300)
+        finally:
+            graph.close()
+    finally:
+        op.close()
