@@ -43,6 +43,8 @@ def parse():
                    help="JSON file of earlier autotuner choices (read, and written on a miss)")
     p.add_argument("--precision", choices=("fp32", "bf16", "fp16"), default="fp32",
                    help="headline leg: FP32, or FP32 data with bf16 / fp16 projection GEMMs")
+    p.add_argument("--no-lifting", action="store_true",
+                   help="skip the BR1 lifting leg (config.lifting)")
     p.add_argument("--tuning", default=None,
                    help="VARIANT,TILE,GRID: launch the headline leg with this tuning on every "
                         "interface instead of autotuning it")
@@ -121,8 +123,18 @@ def algorithmic_bytes(spec):
     return total
 
 
+def lifting_bytes(spec):
+    """Bytes one lifting launch must move: both sides' states in (plus the static metrics
+    if they are per point) and both sides' 15 output values per face point out."""
+    b = 8 if spec.precision == 0 else 4
+    total = (5 * 2 + 15 * 2) * b * spec.P * spec.n_pairs
+    if spec.metrics is not None:
+        total += 4 * b * spec.P * spec.n_pairs
+    return total
+
+
 def run_leg(M, W, specs, disp, steps, warmup, rotate_bytes, graph=False, plain=False, tune=True,
-            tune_cache=None, fixed=None):
+            tune_cache=None, fixed=None, measure_lifting=False):
     """Times one precision of a workload.  plain: one handle (one launch) per interface
     instead of the batched persistent launch; graph: each stage replays a captured HIP
     graph instead of eager launches; tune: the library's autotuner picks each launch
@@ -248,6 +260,35 @@ def run_leg(M, W, specs, disp, steps, warmup, rotate_bytes, graph=False, plain=F
         evs[k][1].record()
     torch.cuda.synchronize()
     kms = np.array([a.elapsed_time(b) for a, b in evs])
+
+    # the BR1 lifting surface term through the same operator (one launch per interface),
+    # timed the same way; inputs rotate with the flux sets
+    lift = None
+    if measure_lifting:
+        dt = torch.float64 if specs[0].precision == W.FP64 else torch.float32
+        louts = [(torch.zeros((3, 5, sp.P, sp.n_face_static), dtype=dt, device="cuda"),
+                  torch.zeros((3, 5, sp.P, sp.n_face_moving), dtype=dt, device="cuda")) for sp in specs]
+
+        def lift_only(per):
+            for i, op in enumerate(ops):
+                sel = [i] if plain else range(len(specs))
+                op.lifting([per[j]["Us"] for j in sel], [per[j]["Um"] for j in sel],
+                           [louts[j][0] for j in sel], [louts[j][1] for j in sel])
+
+        for k in range(3):
+            lift_only(sets[k % nsets])
+        torch.cuda.synchronize()
+        r0.record()
+        for k in range(steps):
+            lift_only(sets[k % nsets])
+        r1.record()
+        torch.cuda.synchronize()
+        lms = r0.elapsed_time(r1) / steps
+        lbytes = sum(lifting_bytes(sp) for sp in specs)
+        lift = {"kernel_ms_avg": lms, "bytes_per_launch": lbytes,
+                "achieved_GBs": lbytes / (lms * 1e-3) / 1e9,
+                "frac": lbytes / (lms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        del louts
     cons = []
     for i, op in enumerate(ops):
         sel = [i] if plain else range(len(specs))
@@ -274,6 +315,7 @@ def run_leg(M, W, specs, disp, steps, warmup, rotate_bytes, graph=False, plain=F
         "achieved_GBs": achieved,
         "frac": achieved / HBM_PEAK_GBS,
         "conservation_rel_residual": cons_rel,
+        "lifting": lift,
         "conservation_rel_residual_last_step": step_cons_rel,
         "rotated_sets": nsets,
         "tuning": tuning,
@@ -357,7 +399,8 @@ def main():
     specs32, disp = W.config(a.config, precision=prec)
     fixed = None if a.tuning is None else tuple(int(x) for x in a.tuning.split(","))
     r32 = run_leg(M, W, specs32, disp, a.steps, a.warmup, a.rotate_bytes, graph=a.graph,
-                  tune=not a.no_autotune, tune_cache=a.tune_cache, fixed=fixed)
+                  tune=not a.no_autotune, tune_cache=a.tune_cache, fixed=fixed,
+                  measure_lifting=not a.no_lifting)
     r64 = None
     if not a.no_fp64:
         specs64, _ = W.config(a.config, precision=W.FP64)
@@ -411,7 +454,8 @@ def main():
                                                        "kernel_ms_max_event_pair",
                                                        "kernel_pts_per_s",
                                                        "conservation_rel_residual",
-                                                       "rotated_sets", "tuning")}},
+                                                       "rotated_sets", "tuning")},
+                   "lifting": r32["lifting"]},
         "roofline": {"bound": "hbm", "achieved": r32["achieved_GBs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": r32["frac"],
                      "traffic": measured_traffic(a.config, a.precision, r32["tuning"]),

@@ -121,6 +121,22 @@ int mortar_flux(mortar_handle *h, const void *const *U_s, const void *const *U_m
                 const void *const *G_s, const void *const *G_m, void *const *F_s,
                 void *const *F_m, void *stream);
 
+/* The BR1 lifting surface term of every interface: the gradients of the first
+ * Bassi-Rebay method (Sec. 2) lift the interface average of the state, and on a sliding
+ * interface that average passes through the same mortar operator as the flux (Sec. 3.3
+ * steps 2-5, Sec. 4.1: the second pair of exchanges).  At every mortar node
+ * U* = (U_static + U_moving) / 2 is formed, multiplied by each component of the static
+ * normal and by the surface element, and projected back onto both sides' faces.
+ * U_s[i], U_m[i]: states [5][P][n_face] as for mortar_flux; L_s[i], L_m[i]: outputs
+ * [3][5][P][n_face] (component d, variable v, as the gradient inputs), the same values
+ * on both sides (static normal; the caller applies the sign).  Only the interface's
+ * columns are written.  Always the VALU-projection kernel, one launch per interface;
+ * in the bf16/fp16 modes it runs in FP32 (their element type).  UNSUPPORTED when an
+ * output array reaches 2 GiB.  Asynchronous on stream; no allocation.  NOT_READY before
+ * the first displacement update. */
+int mortar_lifting(mortar_handle *h, const void *const *U_s, const void *const *U_m,
+                   void *const *L_s, void *const *L_m, void *stream);
+
 /* ---- one stage as a HIP graph (batched persistent launch, Sec. 4.4 multi-interface) --
  * mortar_graph_create captures the flux launch of every interface (one persistent
  * launch when the interfaces share element type, physics and flux) for the given fixed

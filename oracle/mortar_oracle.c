@@ -484,6 +484,12 @@ void orc_point_flux(const double *UL, const double *UR, const double *gL, const 
         for (int v = 0; v < 5; ++v) F[v] = 0.5 * (UL[v] + UR[v]) * dS;
         return;
     }
+    if (riemann >= ORC_LIFT && riemann < ORC_LIFT + 3) {
+        /* BR1 lifting (Sec. 2): U* = (U_L + U_R)/2, component d of U* n dS */
+        const double nd = nrm[riemann - ORC_LIFT];
+        for (int v = 0; v < 5; ++v) F[v] = 0.5 * (UL[v] + UR[v]) * nd * dS;
+        return;
+    }
     if (riemann == ORC_LF) flux_lf(UL, UR, nrm, gamma, Fc);
     else flux_roe(UL, UR, nrm, gamma, riemann != ORC_ROE_NOFIX, Fc);
     if (physics == ORC_NS) {

@@ -27,8 +27,10 @@ enum { ORC_GAUSS = 0, ORC_LGL = 1 };
 enum { ORC_EULER = 0, ORC_NS = 1 };
 /* ORC_AVG is a test-only "flux": the arithmetic mean of both mortar states
  * (linear, so projection exactness can be checked through the whole operator).
- * ORC_ROE_NOFIX is Roe's flux without the entropy fix (test reference only). */
-enum { ORC_LF = 0, ORC_ROE = 1, ORC_ROE_NOFIX = 2, ORC_AVG = 99 };
+ * ORC_ROE_NOFIX is Roe's flux without the entropy fix (test reference only).
+ * ORC_LIFT + d (d = 0, 1, 2) is the BR1 lifting surface flux of the first Bassi-Rebay
+ * method (Sec. 2): the mean of both states times normal component d and dS. */
+enum { ORC_LF = 0, ORC_ROE = 1, ORC_ROE_NOFIX = 2, ORC_AVG = 99, ORC_LIFT = 100 };
 
 typedef struct {
     int N;                 /* polynomial degree */

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 GAUSS, LGL = 0, 1
 EULER, NS = 0, 1
-LF, ROE, ROE_NOFIX, AVG = 0, 1, 2, 99
+LF, ROE, ROE_NOFIX, AVG, LIFT = 0, 1, 2, 99, 100
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -210,6 +210,19 @@ def mortar_flux(spec, n: int, s: float, Us, Um, Gs=None, Gm=None, rows=None):
     if rc:
         raise RuntimeError(f"oracle mortar_flux failed ({rc})")
     return Fs, Fm
+
+
+def mortar_lifting(spec, n: int, s: float, Us, Um, rows=None):
+    """BR1 lifting surface term through the same operator (FP64): for each normal
+    component d the mean of both mortar states times n_d dS, projected back onto both
+    sides.  Returns Ls, Lm of shape [3][5][P][n_face]."""
+    import copy
+    comp = []
+    for d in range(3):
+        sp = copy.copy(spec)
+        sp.physics, sp.riemann = EULER, LIFT + d
+        comp.append(mortar_flux(sp, n, s, Us, Um, rows=rows))
+    return np.stack([c[0] for c in comp]), np.stack([c[1] for c in comp])
 
 
 def sort_mortars(tuples, m_col0: int, m_cols: int):

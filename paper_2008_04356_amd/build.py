@@ -17,7 +17,7 @@ OUT = os.path.join(HERE, "libmortar.so")
 ARCH = os.environ.get("MORTAR_ARCH", "gfx950")
 
 SOURCES = ["mortar_capi.hip", "k_topology.hip", "k_flux_f32.hip", "k_flux_f64.hip",
-           "k_flux_wide_f32.hip", "k_flux_hyb_f32.hip",
+           "k_flux_wide_f32.hip", "k_flux_hyb_f32.hip", "k_lift.hip",
            "k_flux_rd_f32.hip", "k_flux_rd_f64.hip", "k_flux_rd_bf16.hip",
            "k_flux_rd_fp16.hip", "k_flux_rd_batch_f32.hip",
            "k_flux_mfma_f32.hip", "k_flux_mfma_f64.hip", "k_flux_batch_f32.hip",

@@ -172,19 +172,23 @@ constexpr int pick_tile(int budget)
     return best;
 }
 
-template <typename T, int NP, bool NSV, bool MET, int BUDGET>
+// LIFT: the BR1 lifting surface term instead of the flux: states only in, 15 values
+// (3 normal components x 5 variables) per point out.
+template <typename T, int NP, bool NSV, bool MET, int BUDGET, bool LIFT = false>
 struct FluxCfg {
     static constexpr int V = NSV ? 20 : 5;         // projected values per side
     static constexpr int VS = V + (MET ? 4 : 0);   // the static side also carries metrics
     static constexpr int NN = NP * NP;
-    static constexpr int TF = pick_tile<T, NP, VS, V>(BUDGET);
+    static constexpr int NOUT = LIFT ? 15 : 5;     // values per output point
+    static constexpr int ROWS = VS + V > NOUT ? VS + V : NOUT;   // LDS rows of NP x LD
+    static constexpr int TF = pick_tile<T, NP, ROWS, 0>(BUDGET);
     static constexpr int LD = 2 * TF + 4;           // row length; columns 2TF+2, 2TF+3: dead writes
     static constexpr int NIT_S = VS * (TF + 1);
     static constexpr int NIT_M = V * (TF + 1);
     static constexpr int ITEMS = ((NIT_S > NIT_M ? NIT_S : NIT_M) + kHalf - 1) / kHalf;
     static constexpr int ROUNDS = ((2 * TF + 1) * NP + kFluxThreads - 1) / kFluxThreads;
-    static constexpr int ITEMS3 = (5 * TF + kHalf - 1) / kHalf;   // back projection, per side
-    static constexpr int LDS_T = (VS + V) * NP * LD;    // state region (elements of T)
+    static constexpr int ITEMS3 = (NOUT * TF + kHalf - 1) / kHalf;   // back projection, per side
+    static constexpr int LDS_T = ROWS * NP * LD;    // state region (elements of T)
 };
 
 struct TileGeom {
@@ -340,21 +344,69 @@ __device__ __forceinline__ void flux_points(const FluxArgs<T> &a, int nf, const 
     __syncthreads();
 }
 
+// Phase 2 of a lifting tile: thread <-> mortar node, the BR1 average of both sides'
+// states times each component of the static normal and the surface element (Sec. 2:
+// the gradients of the first Bassi-Rebay method lift the interface average of U), 15
+// values per node written over the state region as [3][5][NP][LD] (component d,
+// variable v at row 5 d + v, slot ms at column ms).  Starts after and ends with a barrier.
+template <typename T, int NP, bool MET, int LD, int ROUNDS>
+__device__ __forceinline__ void lift_points(const FluxArgs<T> &a, int nf, const T *ldsS, const T *ldsM,
+                                            T *ldsF)
+{
+    const int tid = threadIdx.x;
+    const int nm = 2 * nf + 1;
+    const int npts = nm * NP;
+    T res[ROUNDS][15];
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+        const int pt = tid + r * kFluxThreads;
+        if (pt < npts) {
+            const int q = pt / nm;
+            const int ms = pt - q * nm;
+            T n[3] = {a.nx, a.ny, a.nz}, dS = a.dS;
+            if (MET) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) n[d] = ldsS[((5 + d) * NP + q) * LD + ms + 1];
+                dS = ldsS[(8 * NP + q) * LD + ms + 1];
+            }
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                const T avg = T(0.5) * (ldsS[(v * NP + q) * LD + ms + 1] + ldsM[(v * NP + q) * LD + ms]) * dS;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) res[r][5 * d + v] = avg * n[d];
+            }
+        }
+    }
+    __syncthreads();   // the output region overwrites states still being read
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+        const int pt = tid + r * kFluxThreads;
+        if (pt < npts) {
+            const int q = pt / nm;
+            const int ms = pt - q * nm;
+#pragma unroll
+            for (int o = 0; o < 15; ++o) ldsF[(o * NP + q) * LD + ms] = res[r][o];
+        }
+    }
+    __syncthreads();
+}
+
 // LDS bytes of one instantiation (state region + matrices).
-template <typename T, int NP, bool NSV, bool MET, int BUDGET>
+template <typename T, int NP, bool NSV, bool MET, int BUDGET, bool LIFT = false>
 constexpr size_t flux_smem_bytes()
 {
-    using C = FluxCfg<T, NP, NSV, MET, BUDGET>;
+    using C = FluxCfg<T, NP, NSV, MET, BUDGET, LIFT>;
     return ((size_t)C::LDS_T * sizeof(T) + 15) / 16 * 16 + (size_t)8 * C::NN * sizeof(T);
 }
 
 // All tiles of one interface that this workgroup's cursor visits (the cursor is valid
 // on entry).  smem holds flux_smem_bytes() bytes, 16-aligned.  Ends with a barrier, so
 // the caller may reuse smem at once.
-template <typename T, int NP, bool NSV, bool MET, int RIEM, int BUDGET, bool CONS = true>
+template <typename T, int NP, bool NSV, bool MET, int RIEM, int BUDGET, bool CONS = true, bool LIFT = false>
 __device__ __forceinline__ void run_interface(const FluxArgs<T> &a, TileCursor &cur, char *smem)
 {
-    using C = FluxCfg<T, NP, NSV, MET, BUDGET>;
+    using C = FluxCfg<T, NP, NSV, MET, BUDGET, LIFT>;
+    constexpr int NOUT = C::NOUT;
     constexpr int V = C::V, VS = C::VS, NN = C::NN, TF = C::TF, LD = C::LD, P = NN;
     static_assert(C::LDS_T * sizeof(T) >= assemble_scratch<NP>() * sizeof(double), "assembly scratch");
 
@@ -383,8 +435,8 @@ __device__ __forceinline__ void run_interface(const FluxArgs<T> &a, TileCursor &
     // start of tile t the input columns of tile t+2 and the output columns of tile t+1
     // are looked up, so every column is in registers before the loads that retire it are
     // waited for.
-    const buf_rsrc_t rF = side ? buf_rsrc(a.Fm, (uint32_t)(5 * plane_m * sizeof(T)))
-                               : buf_rsrc(a.Fs, (uint32_t)(5 * plane_s * sizeof(T)));
+    const buf_rsrc_t rF = side ? buf_rsrc(a.Fm, (uint32_t)(NOUT * plane_m * sizeof(T)))
+                               : buf_rsrc(a.Fs, (uint32_t)(NOUT * plane_s * sizeof(T)));
     const uint32_t nfo = side ? a.nfm : a.nfs;
     TileGeom g = tile_geom(a, cur.tile(), NP);
     cur.next();
@@ -462,7 +514,8 @@ __device__ __forceinline__ void run_interface(const FluxArgs<T> &a, TileCursor &
         __syncthreads();
 
         // ---- phase 2: flux at every mortar node -------------------------------------
-        flux_points<T, NP, NSV, MET, RIEM, LD, C::ROUNDS>(a, g.nf, ldsS, ldsM, ldsF);
+        if constexpr (LIFT) lift_points<T, NP, MET, LD, C::ROUNDS>(a, g.nf, ldsS, ldsM, ldsF);
+        else flux_points<T, NP, NSV, MET, RIEM, LD, C::ROUNDS>(a, g.nf, ldsS, ldsM, ldsF);
 
         // ---- phase 3: back projection, threads 0-127 static, 128-255 moving ----------
         // static face i0+f: mortars (i0+f, 0) slot 2f+1 and (i0+f, 1) slot 2f+2
@@ -478,7 +531,7 @@ __device__ __forceinline__ void run_interface(const FluxArgs<T> &a, TileCursor &
                 const int e = lt + k3 * kHalf;
                 const int ve = e / TF;
                 const int f = e - ve * TF;
-                const int v = min(ve, 4);
+                const int v = min(ve, NOUT - 1);
                 const T *src = ldsF + v * NP * LD;
                 const int s0 = side ? 2 * f : 2 * f + 1;
                 T lo[NP], hi[NP];
@@ -488,7 +541,7 @@ __device__ __forceinline__ void run_interface(const FluxArgs<T> &a, TileCursor &
                     hi[q] = src[q * LD + s0 + 1];
                 }
                 // every lane stores; a dead item's offset lies beyond the array
-                const bool ok = e < 5 * TF && f < g.nf;
+                const bool ok = e < NOUT * TF && f < g.nf;
                 const uint32_t o0 = ((uint32_t)(v * NN + NP * g.pp) * nfo + (uint32_t)col3[k3]) * (uint32_t)sizeof(T);
                 double ls = 0.0, lm = 0.0;       // this face line's w_j-weighted sums
 #pragma unroll
@@ -504,7 +557,7 @@ __device__ __forceinline__ void run_interface(const FluxArgs<T> &a, TileCursor &
                     ls += y;
                     lm += fabs(y);
                 }
-                if (CONS && a.cons && ok) {
+                if (CONS && !LIFT && a.cons && ok) {
                     const double wl = a.basis->w[g.pp];
                     csum[k3] += wl * ls;
                     cmag[k3] += wl * lm;
@@ -525,32 +578,34 @@ __device__ __forceinline__ void run_interface(const FluxArgs<T> &a, TileCursor &
     // conservation partials: per (variable, side) group, one side at a time, thread v
     // adds the side's items e = v TF .. v TF + TF - 1 (thread e % 128, item e / 128) in a
     // fixed order
-    if (CONS && a.cons) {
+    if constexpr (CONS && !LIFT) {
         static_assert(C::LDS_T * sizeof(T) >= (size_t)kHalf * C::ITEMS3 * 2 * sizeof(double),
                       "conservation staging");
-        double *red = reinterpret_cast<double *>(smem);
-        for (int sd = 0; sd < 2; ++sd) {
-            if (side == sd) {
+        if (a.cons) {
+            double *red = reinterpret_cast<double *>(smem);
+            for (int sd = 0; sd < 2; ++sd) {
+                if (side == sd) {
 #pragma unroll
-                for (int k = 0; k < C::ITEMS3; ++k) {
-                    red[(lt * C::ITEMS3 + k) * 2 + 0] = csum[k];
-                    red[(lt * C::ITEMS3 + k) * 2 + 1] = cmag[k];
+                    for (int k = 0; k < C::ITEMS3; ++k) {
+                        red[(lt * C::ITEMS3 + k) * 2 + 0] = csum[k];
+                        red[(lt * C::ITEMS3 + k) * 2 + 1] = cmag[k];
+                    }
                 }
-            }
-            __syncthreads();
-            if (tid < 5) {
-                ConsSum t;
-                double m = 0.0;
-                for (int e = tid * TF; e < (tid + 1) * TF; ++e) {
-                    const double *r = red + ((e % kHalf) * C::ITEMS3 + e / kHalf) * 2;
-                    t.add(r[0]);
-                    m += r[1];
+                __syncthreads();
+                if (tid < 5) {
+                    ConsSum t;
+                    double m = 0.0;
+                    for (int e = tid * TF; e < (tid + 1) * TF; ++e) {
+                        const double *r = red + ((e % kHalf) * C::ITEMS3 + e / kHalf) * 2;
+                        t.add(r[0]);
+                        m += r[1];
+                    }
+                    const size_t o = ((size_t)(2 * tid + sd) * gridDim.x + blockIdx.x) * 2;
+                    a.cons[o + 0] = t.value();
+                    a.cons[o + 1] = m;
                 }
-                const size_t o = ((size_t)(2 * tid + sd) * gridDim.x + blockIdx.x) * 2;
-                a.cons[o + 0] = t.value();
-                a.cons[o + 1] = m;
+                __syncthreads();
             }
-            __syncthreads();
         }
     }
 }
@@ -565,6 +620,17 @@ __global__ __launch_bounds__(kFluxThreads) void k_mortar_flux(FluxArgs<T> a)
         return;
     }
     run_interface<T, NP, NSV, MET, RIEM, BUDGET>(a, cur, smem);
+}
+
+// The BR1 lifting surface term of one interface (a.Fs / a.Fm: [3][5][P][n_face] outputs;
+// a.Gs / a.Gm unused).
+template <typename T, int NP, bool MET, int BUDGET>
+__global__ __launch_bounds__(kFluxThreads) void k_mortar_lift(FluxArgs<T> a)
+{
+    __shared__ __attribute__((aligned(16))) char smem[flux_smem_bytes<T, NP, false, MET, BUDGET, true>()];
+    TileCursor cur(a.n_tiles);
+    if (!cur.valid()) return;               // uniform over the workgroup
+    run_interface<T, NP, false, MET, 0, BUDGET, false, true>(a, cur, smem);
 }
 
 // ---- several interfaces in one persistent launch ---------------------------------------

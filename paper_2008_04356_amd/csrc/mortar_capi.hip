@@ -26,6 +26,10 @@ hipError_t launch_flux_wide_f32(const FluxArgs<float> &a, int NP, int grid, bool
                                 int riem, hipStream_t st);
 int flux_occupancy_f64(int NP, bool ns, bool met, int riem);
 int flux_hyb_occupancy_f32(int NP, bool ns, bool met, int riem);
+int lift_occupancy(int NP, bool met, bool f64);
+int lift_tile_capacity(int NP, bool met, bool f64);
+hipError_t launch_lift_f32(const FluxArgs<float> &a, int NP, int grid, bool met, hipStream_t st);
+hipError_t launch_lift_f64(const FluxArgs<double> &a, int NP, int grid, bool met, hipStream_t st);
 int flux_hyb_tile_capacity_f32(int NP, bool ns, bool met);
 hipError_t launch_flux_hyb_f32(const FluxArgs<float> &a, int NP, int grid, bool ns, bool met,
                                int riem, hipStream_t st);
@@ -641,6 +645,44 @@ int mortar_flux(mortar_handle *h, const void *const *U_s, const void *const *U_m
         const bool ns = f.d.physics == MORTAR_NAVIER_STOKES;
         TRY_HIP(launch_flux(f, h->n_cu, U_s[i], U_m[i], ns ? G_s[i] : nullptr,
                             ns ? G_m[i] : nullptr, F_s[i], F_m[i], st));
+    }
+    return MORTAR_OK;
+}
+
+int mortar_lifting(mortar_handle *h, const void *const *U_s, const void *const *U_m,
+                   void *const *L_s, void *const *L_m, void *stream)
+{
+    if (!h || !U_s || !U_m || !L_s || !L_m) return MORTAR_ERR_INVALID_ARG;
+    for (size_t i = 0; i < h->ifs.size(); ++i) {
+        const Iface &f = h->ifs[i];
+        if (!f.ready) return MORTAR_ERR_NOT_READY;
+        if (!U_s[i] || !U_m[i] || !L_s[i] || !L_m[i]) return MORTAR_ERR_INVALID_ARG;
+        const int64_t nf = std::max<int64_t>(f.d.n_face_static, f.d.n_face_moving);
+        if (15 * (int64_t)f.P * nf * (int64_t)f.elem >= ((int64_t)1 << 31)) return MORTAR_ERR_UNSUPPORTED;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    for (size_t i = 0; i < h->ifs.size(); ++i) {
+        const Iface &f = h->ifs[i];
+        const bool met = f.d_metrics != nullptr, f64 = f.elem == 8;
+        // tiles of the lifting kernel's capacity, balanced along the row (fill_args uses
+        // the flux launch's tuning, so the fields are set here)
+        const int cap = lift_tile_capacity(f.NP, met, f64);
+        const int tiles_per_row = (f.d.n_par + cap - 1) / cap;
+        const int tile_len = (f.d.n_par + tiles_per_row - 1) / tiles_per_row;
+        const int n_tiles = tiles_per_row * f.NP * f.d.n_perp;
+        const int grid = std::max(1, std::min(n_tiles, lift_occupancy(f.NP, met, f64) * h->n_cu));
+        int nt = 0;
+        if (f64) {
+            FluxArgs<double> a;
+            fill_args(f, U_s[i], U_m[i], nullptr, nullptr, L_s[i], L_m[i], a, nt);
+            a.tiles_per_row = tiles_per_row; a.tile_len = tile_len; a.n_tiles = n_tiles;
+            TRY_HIP(launch_lift_f64(a, f.NP, grid, met, st));
+        } else {
+            FluxArgs<float> a;
+            fill_args(f, U_s[i], U_m[i], nullptr, nullptr, L_s[i], L_m[i], a, nt);
+            a.tiles_per_row = tiles_per_row; a.tile_len = tile_len; a.n_tiles = n_tiles;
+            TRY_HIP(launch_lift_f32(a, f.NP, grid, met, st));
+        }
     }
     return MORTAR_OK;
 }

@@ -64,6 +64,7 @@ def _load():
     L.mortar_update_displacement.argtypes = [C.c_void_p, _dp, C.c_void_p]
     L.mortar_update_displacement_ns.argtypes = [C.c_void_p, C.POINTER(C.c_int64), _dp, C.c_void_p]
     L.mortar_flux.argtypes = [C.c_void_p, _vpp, _vpp, _vpp, _vpp, _vpp, _vpp, C.c_void_p]
+    L.mortar_lifting.argtypes = [C.c_void_p, _vpp, _vpp, _vpp, _vpp, C.c_void_p]
     L.mortar_destroy.argtypes = [C.c_void_p]
     L.mortar_error_string.argtypes = [C.c_int]
     L.mortar_error_string.restype = C.c_char_p
@@ -128,6 +129,11 @@ def mortar_flux(h, Us, Um, Gs, Gm, Fs, Fm, stream: int = 0) -> int:
     """Each argument: a sequence of device addresses (ints) or None entries."""
     return lib.mortar_flux(h, _ptrs(Us), _ptrs(Um), _ptrs(Gs), _ptrs(Gm), _ptrs(Fs), _ptrs(Fm),
                            C.c_void_p(stream))
+
+
+def mortar_lifting(h, Us, Um, Ls, Lm, stream: int = 0) -> int:
+    """Each argument: a sequence of device addresses (ints)."""
+    return lib.mortar_lifting(h, _ptrs(Us), _ptrs(Um), _ptrs(Ls), _ptrs(Lm), C.c_void_p(stream))
 
 
 def mortar_graph_create(h, Us, Um, Gs, Gm, Fs, Fm):
@@ -271,6 +277,11 @@ class MortarOperator:
         p = lambda ts: None if ts is None else [None if t is None else t.data_ptr() for t in ts]  # noqa: E731
         _check(mortar_flux(self.h, p(Us), p(Um), p(Gs), p(Gm), p(Fs), p(Fm), self._stream(stream)),
                "mortar_flux")
+
+    def lifting(self, Us, Um, Ls, Lm, stream=None):
+        """BR1 lifting surface term: Ls[i], Lm[i] [3][5][P][n_face] tensors (written)."""
+        p = lambda ts: [t.data_ptr() for t in ts]  # noqa: E731
+        _check(mortar_lifting(self.h, p(Us), p(Um), p(Ls), p(Lm), self._stream(stream)), "mortar_lifting")
 
     def tuning_key(self):
         """What a tuning depends on: the device, and every interface's shape and mode."""
