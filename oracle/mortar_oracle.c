@@ -24,7 +24,10 @@
  * Where the paper is silent or garbled this code takes one reading each: the node set
  * is a parameter, the sub-intervals are named by their position on the face, the Roe
  * solver carries the Harten-Hyman fix on the acoustic fields only, BR1 uses gradients
- * of the conservative variables, and a sliding interface has no grid-velocity term.
+ * of the conservative variables, a sliding interface has no grid-velocity term, and
+ * per-point metrics (curved interfaces, Fig. of interface shapes) give the flux the
+ * static side's interpolated normal scaled to unit length and its interpolated surface
+ * element.
  *
  * Compiled with -ffp-contract=off: every product and sum is rounded as written.
  */
@@ -628,7 +631,13 @@ int orc_mortar_flux(const orc_iface *dsc, int64_t n, double s,
                                     a += dsc->metrics[((int64_t)c * P + j + NP * pp) * ns_ + cs] * ls[j];
                                 mv[c] = a;
                             }
-                            nrm[0] = mv[0]; nrm[1] = mv[1]; nrm[2] = mv[2]; dS = mv[3];
+                            /* On a curved face the interpolant of unit nodal normals is
+                             * shorter than one between the nodes: the flux takes the
+                             * interpolated direction, scaled to unit length, and the
+                             * interpolated surface element. */
+                            double len = sqrt(mv[0] * mv[0] + mv[1] * mv[1] + mv[2] * mv[2]);
+                            nrm[0] = mv[0] / len; nrm[1] = mv[1] / len; nrm[2] = mv[2] / len;
+                            dS = mv[3];
                         } else {
                             nrm[0] = dsc->normal[0]; nrm[1] = dsc->normal[1]; nrm[2] = dsc->normal[2];
                             dS = dsc->dS;

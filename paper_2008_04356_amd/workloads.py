@@ -12,6 +12,10 @@ a turbine LES, Sec. 5) need a full solver and external meshes; these fields stan
 for them with the same shapes: free stream rho = 1, normal velocity 0.3, p = 0.71
 (Mach about 0.3), gamma = 1.4, small smooth perturbations.
 
+Interface shapes (Fig. of the possible 3D interface geometries): plane, plane annular
+axial, and surfaces of revolution (cylindrical radial, conical) with polynomial face
+geometry.
+
 Layouts: U[5][P][n_face], G[3][5][P][n_face] (G[d][v] = dU_v/dx_d), metrics
 M[4][P][n_face] = (nx, ny, nz, dS); point p = p_par + (N+1) * p_perp; the face of
 (i_par, i_perp) sits in column face_id[i_perp, i_par].
@@ -27,7 +31,7 @@ import numpy as np
 GAUSS, LGL = 0, 1
 EULER, NS = 0, 1
 LF, ROE = 0, 1
-PLANE, ANNULUS = 0, 1
+PLANE, ANNULUS, REVOLUTION = 0, 1, 2
 FP64, FP32, BF16_MFMA, FP16_MFMA = 0, 1, 2, 3
 
 FREE_STREAM = dict(rho=1.0, vn=0.3, p=0.71)
@@ -56,7 +60,9 @@ class InterfaceSpec:
     n_face_moving: int = 0
     owner_static: Optional[np.ndarray] = None      # [n_perp, n_par] int32 or None
     owner_moving: Optional[np.ndarray] = None
-    r_edges: Optional[np.ndarray] = None           # annulus radii [n_perp + 1]
+    r_edges: Optional[np.ndarray] = None           # annulus radii / generatrix edges [n_perp + 1]
+    beta: float = 0.0                              # surface of revolution: cone half-angle
+    r0: float = 1.0                                # surface of revolution: radius at s = 0
     name: str = ""
 
     @property
@@ -154,6 +160,87 @@ def make_annulus(N: int, n_par: int, n_perp: int, seed: int, physics: int = NS,
                          n_face_static=nfs, n_face_moving=nfm, r_edges=r_edges, name=name)
 
 
+def revolution_point(beta: float, r0: float, th, s):
+    """Point of the surface of revolution at angle th and generatrix coordinate s:
+    (r cos th, r sin th, z) with r = r0 + s sin(beta), z = s cos(beta).  beta = 0 is the
+    cylinder r = r0 (cylindrical radial interface), 0 < beta < pi/2 a cone (conical
+    interface), beta = pi/2 the flat annulus z = 0."""
+    r = r0 + s * math.sin(beta)
+    return np.stack(np.broadcast_arrays(r * np.cos(th), r * np.sin(th), s * math.cos(beta)))
+
+
+def revolution_frame(beta: float, th):
+    """Unit tangents along the slide (e_th) and the generatrix (e_s), and the normal
+    n = e_s x e_th (the cylinder's points to the axis, the flat annulus's is +e_z)."""
+    ct, st = np.cos(th), np.sin(th)
+    sb, cb = math.sin(beta), math.cos(beta)
+    e_th = np.stack([-st, ct, np.zeros_like(th)])
+    e_s = np.stack([sb * ct, sb * st, np.full_like(th, cb)])
+    n = np.stack([e_s[1] * e_th[2] - e_s[2] * e_th[1],
+                  e_s[2] * e_th[0] - e_s[0] * e_th[2],
+                  e_s[0] * e_th[1] - e_s[1] * e_th[0]])
+    return e_th, e_s, n
+
+
+def make_revolution(N: int, n_par: int, n_perp: int, beta: float, seed: int,
+                    physics: int = NS, riemann: int = ROE, precision: int = FP32,
+                    node_set: int = GAUSS, mu: float = 1e-4, r0: float = 1.0,
+                    length: float = 0.5, exact_metrics: bool = False,
+                    name: str = "") -> InterfaceSpec:
+    """Curved interface on a surface of revolution (cylindrical radial for beta = 0,
+    conical for 0 < beta < pi/2), sliding in theta (l_par in radians), rows along the
+    generatrix with seeded jittered edges in [0, length].
+
+    Each static face is the degree-N polynomial through the exact surface points at its
+    nodes (the face geometry of a high-order mesh).  Its nodal metrics come from that
+    polynomial: a = dX/d(eta) x dX/d(xi) at the node, n = a / |a|, dS = |a|.  With
+    exact_metrics the nodal metrics are the exact surface's instead: n = e_s x e_th,
+    dS = r (l_par/2) (ds/2)."""
+    rng = np.random.Generator(np.random.PCG64(2000 + seed))
+    l_par = 2.0 * math.pi / n_par
+    j = np.arange(n_perp + 1, dtype=np.float64)
+    jitter = rng.uniform(-0.3, 0.3, n_perp + 1)
+    jitter[0] = jitter[-1] = 0.0
+    s_edges = length * (j + jitter) / n_perp
+    fs, nfs = synthetic_face_ids(n_par, n_perp)
+    fm, nfm = synthetic_face_ids(n_par, n_perp)
+    x = node_positions(N, node_set)
+    NP, P = N + 1, (N + 1) ** 2
+    # derivatives of the nodal interpolant at the nodes: D[a, b] = l_b'(x_a), from
+    # numpy's Legendre fit of the cardinal functions
+    leg = np.polynomial.legendre
+    D = leg.legval(x, leg.legder(leg.legfit(x, np.eye(NP), N))).T
+    met = np.zeros((4, P, nfs))
+    for ip in range(n_perp):
+        ds = s_edges[ip + 1] - s_edges[ip]
+        sv = s_edges[ip] + 0.5 * (x + 1.0) * ds                       # [NP] along eta
+        for i in range(n_par):
+            th = (i + 0.5 * (x + 1.0)) * l_par                         # [NP] along xi
+            TH, SV = np.meshgrid(th, sv)                               # [pp, pa]
+            if exact_metrics:
+                _, _, n = revolution_frame(beta, TH)
+                dS = (r0 + SV * math.sin(beta)) * (l_par / 2.0) * (ds / 2.0)
+            else:
+                X = revolution_point(beta, r0, TH, SV)                 # [3, pp, pa]
+                Xxi = np.einsum("ab,cpb->cpa", D, X)
+                Xeta = np.einsum("ab,cbq->caq", D, X)
+                a = np.cross(Xeta, Xxi, axis=0)
+                dS = np.sqrt(np.sum(a * a, axis=0))
+                n = a / dS
+            cols = fs[ip, i]
+            for pp in range(NP):
+                for pa in range(NP):
+                    p = pa + NP * pp
+                    met[0:3, p, cols] = n[:, pp, pa]
+                    met[3, p, cols] = dS[pp, pa]
+    return InterfaceSpec(N=N, n_par=n_par, n_perp=n_perp, l_par=l_par, node_set=node_set,
+                         geometry=REVOLUTION, physics=physics, riemann=riemann,
+                         precision=precision, mu=mu, normal=(0.0, 0.0, 1.0), dS=0.0,
+                         metrics=met, face_id_static=fs, face_id_moving=fm,
+                         n_face_static=nfs, n_face_moving=nfm, r_edges=s_edges, beta=beta,
+                         r0=r0, name=name)
+
+
 def seeded_owners(spec: InterfaceSpec, seed: int, n_static_ranks: int, n_moving_ranks: int):
     """Virtual ranks: contiguous blocks of faces along (i_perp, i_par) per rank, as a
     space-filling-curve partition would give on a structured interface."""
@@ -218,21 +305,36 @@ def _annulus_field(rng, n_modes=32):
 
 
 def _eval_annulus_prim(field, r, th):
+    """Primitive variables and gradients of the annulus field at radius r (shape
+    [n_perp, 1, NP, 1]: rows and their nodes) and angle th (shape [1, n_par, 1, NP]: the
+    slide).  Every mode is separable by the angle-sum rule, so the sums over modes are
+    products of [rows x modes] and [modes x slide] tables."""
     m_theta, kr, kz, amp, phase = field
+    n_perp, _, NP, _ = r.shape
+    n_par = th.shape[1]
+    r1, t1 = r.reshape(-1), th.reshape(-1)
+    B = np.outer(r1 - 0.8, kr)                       # [n_r, modes]
+    sB, cB = np.sin(B), np.cos(B)
+    ct, st, ir = np.cos(t1)[None, :], np.sin(t1)[None, :], (1.0 / r1)[:, None]
     base = np.array([FREE_STREAM["rho"], 0.0, 0.0, FREE_STREAM["vn"], FREE_STREAM["p"]])
-    q = np.empty((5,) + r.shape)
-    dq = np.zeros((3, 5) + r.shape)
-    ct, st = np.cos(th), np.sin(th)
+
+    def grid(x):                                     # [n_r, n_t] -> [n_perp, n_par, NP, NP]
+        return x.reshape(n_perp, NP, n_par, NP).transpose(0, 2, 1, 3)
+
+    q = np.empty((5, n_perp, n_par, NP, NP))
+    dq = np.empty((3, 5, n_perp, n_par, NP, NP))
     for v in range(5):
-        q[v] = base[v]
-        for m in range(len(m_theta)):
-            arg = m_theta[m] * th + kr[m] * (r - 0.8) + phase[v, m]
-            q[v] += amp[v, m] * np.sin(arg)
-            c = amp[v, m] * np.cos(arg)
-            dr, dth = c * kr[m], c * m_theta[m]
-            dq[0, v] += ct * dr - st / r * dth
-            dq[1, v] += st * dr + ct / r * dth
-            dq[2, v] += c * kz[m]
+        A = np.outer(t1, m_theta) + phase[v][None, :]     # [n_t, modes]
+        sA, cA = np.sin(A) * amp[v], np.cos(A) * amp[v]
+        # sum_m amp sin(A + B) and sum_m w_m amp cos(A + B)
+        q[v] = grid(base[v] + cB @ sA.T + sB @ cA.T)
+
+        def csum(w):
+            return (cB * w) @ cA.T - (sB * w) @ sA.T
+        x_r, x_t = csum(kr), csum(m_theta.astype(np.float64))
+        dq[0, v] = grid(ct * x_r - (st * ir) * x_t)
+        dq[1, v] = grid(st * x_r + (ct * ir) * x_t)
+        dq[2, v] = grid(csum(kz))
     return q, dq
 
 
@@ -273,13 +375,27 @@ def make_inputs(spec: InterfaceSpec, seed: int, delta: float = 0.0, noise: float
             y, z = np.broadcast_arrays(y, z)
             q, dq = _eval_plane_prim(field, y, z)
             out[side] = _prim_to_cons(q, dq, spec.gamma)
+    elif spec.geometry == REVOLUTION:
+        field = _annulus_field(rng)
+        se = spec.r_edges
+        for side, shift in (("s", 0.0), ("m", delta)):
+            th = (ia + 0.5 * (xa + 1.0)) * spec.l_par + shift
+            sv = se[:-1][:, None, None, None] + 0.5 * (xp + 1.0) * np.diff(se)[:, None, None, None]
+            # the annulus field with its radius running over [0.8, 1] along the generatrix;
+            # its velocity components (x, y, z) become components along (e_th, e_s, n), so
+            # the free stream crosses the interface with normal velocity 0.3 as elsewhere
+            q, dq = _eval_annulus_prim(field, 0.8 + 0.2 * sv / se[-1], th)
+            e_th, e_s, nrm = revolution_frame(spec.beta, th)   # broadcast over rows
+            q[1:4] = q[1] * e_th + q[2] * e_s + q[3] * nrm
+            for d in range(3):
+                dq[d, 1:4] = dq[d, 1] * e_th + dq[d, 2] * e_s + dq[d, 3] * nrm
+            out[side] = _prim_to_cons(q, dq, spec.gamma)
     else:
         field = _annulus_field(rng)
         re = spec.r_edges
         for side, shift in (("s", 0.0), ("m", delta)):
             th = (ia + 0.5 * (xa + 1.0)) * spec.l_par + shift
             r = re[:-1][:, None, None, None] + 0.5 * (xp + 1.0) * np.diff(re)[:, None, None, None]
-            th, r = np.broadcast_arrays(th, r)
             q, dq = _eval_annulus_prim(field, r, th)
             out[side] = _prim_to_cons(q, dq, spec.gamma)
 
@@ -362,6 +478,16 @@ def config(idx: int, precision: int = None):
         def disp(k):
             return [speeds[i] * k * specs[i].l_par for i in range(3)]
         return specs, disp
+    if idx in (6, 7):
+        # curved interfaces at the annulus workload's size: cylindrical radial (6) and
+        # conical with a 30 degree half-angle (7), polynomial face geometry
+        spec = make_revolution(7, 512, 64, 0.0 if idx == 6 else math.pi / 6, seed=idx,
+                               precision=FP32 if precision is None else precision,
+                               name="cylinder" if idx == 6 else "cone")
+
+        def disp(k):
+            return [0.0137 * k * spec.l_par]
+        return [spec], disp
     if idx == 5:
         spec = make_plane(9, 256, 256, physics=EULER, riemann=ROE,
                           precision=FP32 if precision is None else precision, name="C5")
