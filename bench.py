@@ -411,7 +411,8 @@ def main():
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(M, W, specs32[0], disp, a.cpu_stages)
     kargs = {1: "<float,4,Euler,LF>", 2: "<float,6,NS,Roe>", 3: "<float,8,NS+metrics,Roe>",
-             4: "<float,NS,Roe,N=3,5,7>", 5: "<float,10,Euler,Roe>"}
+             4: "<float,NS,Roe,N=3,5,7>", 5: "<float,10,Euler,Roe>",
+             6: "<float,8,NS+metrics,Roe>", 7: "<float,8,NS+metrics,Roe>"}
     tuned = r32["tuning"][0]["variant"] if r32["tuning"] else 0
     if len(specs32) > 1:
         kernel = ("k_mortar_flux_rd_batch" if tuned == 2 else "k_mortar_flux_batch") + kargs[a.config]
@@ -426,7 +427,11 @@ def main():
                 "Navier-Stokes Roe+BR1, FP32, one persistent launch per stage"
                 + (" (HIP graph)" if a.graph else ""),
              1: f"plane interface N={spec.N}, {spec.n_par}x{spec.n_perp}, Euler LF, FP32",
-             5: f"plane interface N={spec.N}, {spec.n_par}x{spec.n_perp}, Euler Roe, FP32"}
+             5: f"plane interface N={spec.N}, {spec.n_par}x{spec.n_perp}, Euler Roe, FP32",
+             6: f"cylindrical radial interface N={spec.N}, {spec.n_par}x{spec.n_perp} face pairs, "
+                "polynomial face geometry, per-point metrics, Navier-Stokes Roe+BR1, FP32",
+             7: f"conical interface (30 deg) N={spec.N}, {spec.n_par}x{spec.n_perp} face pairs, "
+                "polynomial face geometry, per-point metrics, Navier-Stokes Roe+BR1, FP32"}
     out = {
         "metric": "mortar flux points/sec and HBM GB/s vs peak, batched FP32 vs plain FP64",
         "value": r32["pts_per_s"],

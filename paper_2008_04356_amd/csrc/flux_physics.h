@@ -31,6 +31,21 @@ template <typename T> __device__ __forceinline__ T drcp(T x);
 template <> __device__ __forceinline__ float drcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 template <> __device__ __forceinline__ double drcp<double>(double x) { return 1.0 / x; }
 
+template <typename T> __device__ __forceinline__ T drsqrt(T x);
+template <> __device__ __forceinline__ float drsqrt<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+template <> __device__ __forceinline__ double drsqrt<double>(double x) { return 1.0 / __builtin_sqrt(x); }
+
+// Per-point metrics: on a curved face the interpolant of the unit nodal normals is
+// shorter than one between the nodes, so the flux takes its direction scaled to unit
+// length.  (On a flat face this changes nothing beyond rounding.)
+template <typename T>
+__device__ __forceinline__ void unit_normal(T &nx, T &ny, T &nz) {
+    const T s = drsqrt<T>(nx * nx + ny * ny + nz * nz);
+    nx *= s;
+    ny *= s;
+    nz *= s;
+}
+
 template <typename T> __device__ __forceinline__ T dabs(T x) { return x < T(0) ? -x : x; }
 template <typename T> __device__ __forceinline__ T dmax(T a, T b) { return a > b ? a : b; }
 

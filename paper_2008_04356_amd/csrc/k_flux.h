@@ -312,6 +312,7 @@ __device__ __forceinline__ void flux_points(const FluxArgs<T> &a, int nf, const 
                 ny = ldsS[((V + 1) * NP + q) * LD + ms + 1];
                 nz = ldsS[((V + 2) * NP + q) * LD + ms + 1];
                 dS = ldsS[((V + 3) * NP + q) * LD + ms + 1];
+                unit_normal(nx, ny, nz);
             }
             T F[5];
             convective_flux<T, RIEM>(UL, UR, nx, ny, nz, a.gas, F);
@@ -368,6 +369,7 @@ __device__ __forceinline__ void lift_points(const FluxArgs<T> &a, int nf, const 
 #pragma unroll
                 for (int d = 0; d < 3; ++d) n[d] = ldsS[((5 + d) * NP + q) * LD + ms + 1];
                 dS = ldsS[(8 * NP + q) * LD + ms + 1];
+                unit_normal(n[0], n[1], n[2]);
             }
 #pragma unroll
             for (int v = 0; v < 5; ++v) {

@@ -231,6 +231,7 @@ __global__ __launch_bounds__((MCfg<T, NP, NSV, MET>::NT)) void k_mortar_flux_mfm
                 ny = ldsS[((V + 1) * NP + q) * LD + ms + 1];
                 nz = ldsS[((V + 2) * NP + q) * LD + ms + 1];
                 dS = ldsS[((V + 3) * NP + q) * LD + ms + 1];
+                unit_normal(nx, ny, nz);
             }
             T F[5];
             convective_flux<T, RIEM>(UL, UR, nx, ny, nz, a.gas, F);

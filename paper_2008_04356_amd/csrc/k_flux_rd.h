@@ -477,6 +477,16 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
         if constexpr (MET) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) proj_s(ls[V + c], MT[c]);
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    T nx = MT[0][rb][r], ny = MT[1][rb][r], nz = MT[2][rb][r];
+                    unit_normal(nx, ny, nz);
+                    MT[0][rb][r] = nx;
+                    MT[1][rb][r] = ny;
+                    MT[2][rb][r] = nz;
+                }
         }
 
         // rows of this lane that are mortar nodes the tile needs: mortar (i0-1+col, 0)
