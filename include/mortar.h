@@ -25,7 +25,10 @@
  *   fluxes    F[5][P][n_face]      surface flux times surface element, in the STATIC
  *                                  side's normal direction on both sides (the caller's
  *                                  surface integral applies the sign of each side);
- *   metrics   M[4][P][n_face_s]    static-side (n_x, n_y, n_z, dS) per point.
+ *   metrics   M[4][P][n_face_s]    static-side (n_x, n_y, n_z, dS) per point; both are
+ *                                  interpolated to the mortar nodes and the normal is
+ *                                  scaled to unit length there (on curved interfaces the
+ *                                  interpolant of unit normals is shorter between nodes).
  *   The face (i_par, i_perp) of a side is column face_id[i_perp * n_par + i_par].
  *
  * Ownership: descriptor arrays are host memory owned by the caller and copied during
@@ -53,7 +56,9 @@ typedef enum {
     MORTAR_ERR_NOT_READY = -5    /* mortar_flux before the first displacement update */
 } mortar_status;
 
-enum { MORTAR_GEOM_PLANE = 0, MORTAR_GEOM_ANNULUS = 1 };
+/* Interface shapes of the paper's figure of 3D interface geometries: plane, plane annular
+ * axial, and surfaces of revolution (cylindrical radial, conical). */
+enum { MORTAR_GEOM_PLANE = 0, MORTAR_GEOM_ANNULUS = 1, MORTAR_GEOM_REVOLUTION = 2 };
 enum { MORTAR_NODES_GAUSS = 0, MORTAR_NODES_LGL = 1 };
 enum { MORTAR_EULER = 0, MORTAR_NAVIER_STOKES = 1 };
 enum { MORTAR_FLUX_LF = 0, MORTAR_FLUX_ROE = 1 };
