@@ -268,18 +268,32 @@ __global__ __launch_bounds__(256) void k_cons_partial(const T *__restrict__ Fs,
     }
 }
 
-// Final pass: wave g = v * 2 + side adds its group's partials in a fixed order
-// (compensated lane-stride sums, then the xor tree); out[v][0] = static integral,
-// out[v][1] = moving integral, out[v][2] = sum of |terms|.
+// Final pass: wave g = v * 2 + side adds its group's partials in a fixed order (each
+// lane takes partials lane, lane + 64, ... with compensation, eight loads in flight
+// before any is added, then the xor tree); out[v][0] = static integral, out[v][1] =
+// moving integral, out[v][2] = sum of |terms|.
 __global__ __launch_bounds__(640) void k_cons_final(const double *__restrict__ part, int nb,
                                                     double *__restrict__ out)
 {
     __shared__ double res[10][2];
     const int g = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    constexpr int kAhead = 8;
     Neumaier a, m;
-    for (int b = lane; b < nb; b += 64) {
-        a.add(part[((size_t)g * nb + b) * 2 + 0]);
-        m.add(part[((size_t)g * nb + b) * 2 + 1]);
+    for (int b0 = lane; b0 < nb; b0 += 64 * kAhead) {
+        double va[kAhead], vm[kAhead];
+#pragma unroll
+        for (int k = 0; k < kAhead; ++k) {
+            const int b = b0 + 64 * k;
+            const size_t at = ((size_t)g * nb + (b < nb ? b : 0)) * 2;
+            va[k] = part[at + 0];
+            vm[k] = part[at + 1];
+        }
+#pragma unroll
+        for (int k = 0; k < kAhead; ++k)
+            if (b0 + 64 * k < nb) {
+                a.add(va[k]);
+                m.add(vm[k]);
+            }
     }
     const double sa = cons_wave_add(a.s + a.c), sm = cons_wave_add(m.s + m.c);
     if (lane == 0) {
