@@ -200,22 +200,21 @@ def run_leg(M, W, specs, disp, steps, warmup, rotate_bytes, graph=False, plain=F
     cons_dev = [torch.zeros((1 if plain else len(specs), 5, 3), dtype=torch.float64, device="cuda")
                 for _ in ops]
 
+    # eager stages with their arguments marshalled once per buffer set (update + flux +
+    # conservation sums: three C calls per operator)
+    stages = None if graph else [[op.stage(*args(per, [i] if plain else None), cons_out=cons_dev[i])
+                                  for i, op in enumerate(ops)] for per in sets]
+
     def step(k):
-        per = sets[k % nsets]
         d = disp(k)
         if graph:
+            per = sets[k % nsets]
             graphs[k % nsets].launch(d)
-        elif plain:
-            for i, op in enumerate(ops):
-                op.update([d[i]])
-                op.flux(*args(per, [i]))
+            op = ops[0]
+            op.conservation_device([p["Fs"] for p in per], [p["Fm"] for p in per], cons_dev[0])
         else:
-            ops[0].update(d)
-            ops[0].flux(*args(per))
-        for i, op in enumerate(ops):
-            sel = [i] if plain else range(len(specs))
-            op.conservation_device([per[j]["Fs"] for j in sel], [per[j]["Fm"] for j in sel],
-                                   cons_dev[i])
+            for i, st in enumerate(stages[k % nsets]):
+                st([d[i]] if plain else d)
 
     for k in range(warmup):
         step(k)

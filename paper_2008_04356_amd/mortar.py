@@ -278,6 +278,12 @@ class MortarOperator:
         _check(mortar_flux(self.h, p(Us), p(Um), p(Gs), p(Gm), p(Fs), p(Fm), self._stream(stream)),
                "mortar_flux")
 
+    def stage(self, Us, Um, Gs, Gm, Fs, Fm, cons_out=None, stream=None):
+        """One stage for fixed face buffers with the arguments marshalled once (see
+        MortarStage): stage(disp) runs the displacement update, the flux and, with cons_out,
+        the device conservation sums."""
+        return MortarStage(self, Us, Um, Gs, Gm, Fs, Fm, cons_out, stream)
+
     def lifting(self, Us, Um, Ls, Lm, stream=None):
         """BR1 lifting surface term: Ls[i], Lm[i] [3][5][P][n_face] tensors (written)."""
         p = lambda ts: [t.data_ptr() for t in ts]  # noqa: E731
@@ -368,6 +374,35 @@ class MortarOperator:
         _check(lib.mortar_conservation(self.h, p(Fs), p(Fm), out.ctypes.data_as(_dp),
                                        C.c_void_p(self._stream(stream))), "mortar_conservation")
         return out
+
+
+class MortarStage:
+    """A stage launcher for fixed face buffers: the pointer arrays, the stream and the
+    displacement array are built once, so a call costs three C calls
+    (mortar_update_displacement, mortar_flux, and mortar_conservation_device into cons_out,
+    a float64 device tensor [n_iface, 5, 3], when given).  The stream is the one given, else
+    the current stream at construction."""
+
+    def __init__(self, op, Us, Um, Gs, Gm, Fs, Fm, cons_out=None, stream=None):
+        p = lambda ts: None if ts is None else _ptrs([None if t is None else t.data_ptr() for t in ts])  # noqa: E731
+        self._keep = (op, Us, Um, Gs, Gm, Fs, Fm, cons_out)
+        self._h = op.h
+        self._args = (p(Us), p(Um), p(Gs), p(Gm), p(Fs), p(Fm))
+        self._st = C.c_void_p(op._stream(stream))
+        self._disp = (C.c_double * len(op.specs))()
+        self._cons = None if cons_out is None else \
+            (self._args[4], self._args[5], C.c_void_p(cons_out.data_ptr()))
+
+    def __call__(self, disp):
+        d = self._disp
+        for i, x in enumerate(disp):
+            d[i] = x
+        rc = lib.mortar_update_displacement(self._h, d, self._st)
+        if rc == OK:
+            rc = lib.mortar_flux(self._h, *self._args, self._st)
+        if rc == OK and self._cons is not None:
+            rc = lib.mortar_conservation_device(self._h, *self._cons, self._st)
+        _check(rc, "mortar stage")
 
 
 class MortarGraph:

@@ -309,3 +309,33 @@ def test_fused_conservation_sums(M, precision, variant, tile, grid, n_par):
         assert np.all(np.abs(fused[:, 0] - fused[:, 1]) <= tol * fused[:, 2])
     finally:
         op.close()
+
+
+@pytest.mark.parametrize("variant", [0, 2])
+def test_prepared_stage_equals_separate_calls(M, variant):
+    """MortarStage (arguments marshalled once) gives bitwise the fluxes and conservation
+    sums of the separate update / flux / conservation_device calls, stage after stage."""
+    import torch
+    spec = W.make_plane(5, 37, 3, physics=W.NS, riemann=W.ROE, mu=1e-3, precision=W.FP32,
+                        scramble_seed=2, extra_cols=1)
+    din = H.device_inputs(spec, W.make_inputs(spec, seed=4, noise=1e-3))
+    op = M.MortarOperator([spec])
+    try:
+        assert M.mortar_set_tuning(op.h, 0, variant, 0, 0) == 0
+        a, b = H.alloc_outputs(spec, fill=0.0), H.alloc_outputs(spec, fill=0.0)
+        ca = torch.zeros((1, 5, 3), dtype=torch.float64, device="cuda:0")
+        cb = torch.zeros((1, 5, 3), dtype=torch.float64, device="cuda:0")
+        stage = op.stage([din["Us"]], [din["Um"]], [din["Gs"]], [din["Gm"]], [a[0]], [a[1]],
+                         cons_out=ca)
+        for k in range(4):
+            d = (0.3 + 5.1 * k) * spec.l_par
+            print(f"[parity] prepared stage {k} variant {variant}", flush=True)
+            stage([d])
+            op.update([d])
+            op.flux([din["Us"]], [din["Um"]], [din["Gs"]], [din["Gm"]], [b[0]], [b[1]])
+            op.conservation_device([b[0]], [b[1]], cb)
+            torch.cuda.synchronize()
+            assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+            assert torch.equal(ca, cb)
+    finally:
+        op.close()
