@@ -275,20 +275,31 @@ def _plane_field(rng, n_modes=3):
     return k, amp, phase
 
 
-def _eval_plane_prim(field, y, z):
-    """Primitive (rho, vx, vy, vz, p) and their gradients at x = 0, (y, z) arrays."""
+def _eval_plane_prim(field, y, z, grad=True):
+    """Primitive (rho, vx, vy, vz, p) and their gradients (None without grad) at x = 0,
+    for y of shape [1, n_par, 1, NP] (the slide) and z of shape [n_perp, 1, NP, 1] (rows).
+    Every mode is separable by the angle-sum rule, so the sums over modes are products
+    of [rows x modes] and [modes x slide] tables."""
     k, amp, phase = field
+    n_perp, _, NP, _ = z.shape
+    n_par = y.shape[1]
+    y1, z1 = y.reshape(-1), z.reshape(-1)
+    B = np.outer(z1, k[:, 2])                        # [n_z, modes]
+    sB, cB = np.sin(B), np.cos(B)
     base = np.array([FREE_STREAM["rho"], FREE_STREAM["vn"], 0.0, 0.0, FREE_STREAM["p"]])
-    q = np.empty((5,) + y.shape)
-    dq = np.zeros((3, 5) + y.shape)
+
+    def grid(x):                                     # [n_z, n_y] -> [n_perp, n_par, NP, NP]
+        return x.reshape(n_perp, NP, n_par, NP).transpose(0, 2, 1, 3)
+
+    q = np.empty((5, n_perp, n_par, NP, NP))
+    dq = np.empty((3, 5, n_perp, n_par, NP, NP)) if grad else None
     for v in range(5):
-        q[v] = base[v]
-        for m in range(k.shape[0]):
-            arg = k[m, 1] * y + k[m, 2] * z + phase[v, m]
-            q[v] += amp[v, m] * np.sin(arg)
-            c = amp[v, m] * np.cos(arg)
-            for d in range(3):
-                dq[d, v] += c * k[m, d]
+        A = np.outer(y1, k[:, 1]) + phase[v][None, :]    # [n_y, modes]
+        sA, cA = np.sin(A) * amp[v], np.cos(A) * amp[v]
+        q[v] = grid(base[v] + cB @ sA.T + sB @ cA.T)     # sum_m amp sin(A + B)
+        if grad:
+            for d in range(3):                           # sum_m amp k_d cos(A + B)
+                dq[d, v] = grid((cB * k[:, d]) @ cA.T - (sB * k[:, d]) @ sA.T)
     return q, dq
 
 
@@ -345,6 +356,8 @@ def _prim_to_cons(q, dq, gamma):
     U[0] = rho
     U[1:4] = rho * vel
     U[4] = p / (gamma - 1.0) + 0.5 * rho * np.sum(vel ** 2, axis=0)
+    if dq is None:
+        return U, None
     G = np.empty_like(dq)
     for d in range(3):
         drho, dvel, dp = dq[d, 0], dq[d, 1:4], dq[d, 4]
@@ -372,8 +385,7 @@ def make_inputs(spec: InterfaceSpec, seed: int, delta: float = 0.0, noise: float
         for side, shift in (("s", 0.0), ("m", delta)):
             y = (ia + 0.5 * (xa + 1.0)) * spec.l_par + shift
             z = (ip + 0.5 * (xp + 1.0)) * l_perp
-            y, z = np.broadcast_arrays(y, z)
-            q, dq = _eval_plane_prim(field, y, z)
+            q, dq = _eval_plane_prim(field, y, z, grad=spec.physics == NS)
             out[side] = _prim_to_cons(q, dq, spec.gamma)
     elif spec.geometry == REVOLUTION:
         field = _annulus_field(rng)
@@ -404,13 +416,16 @@ def make_inputs(spec: InterfaceSpec, seed: int, delta: float = 0.0, noise: float
                           ("m", spec.face_id_moving, spec.n_face_moving)):
         U, G = out[side]  # U [5, n_perp, n_par, NP(perp), NP(par)], G [3, 5, ...]
         U = U + noise * rng.uniform(-1.0, 1.0, U.shape)
-        G = G + noise * rng.uniform(-1.0, 1.0, G.shape)
         Ua = np.zeros((5, P, nf))
-        Ga = np.zeros((3, 5, P, nf))
         cols = fid.reshape(-1)
         # point p = p_par + NP * p_perp
         Ua[:, :, cols] = U.transpose(0, 3, 4, 1, 2).reshape(5, P, -1)
-        Ga[:, :, :, cols] = G.transpose(0, 1, 4, 5, 2, 3).reshape(3, 5, P, -1)
+        del U
+        Ga = None
+        if G is not None:
+            G = G + noise * rng.uniform(-1.0, 1.0, G.shape)
+            Ga = np.zeros((3, 5, P, nf))
+            Ga[:, :, :, cols] = G.transpose(0, 1, 4, 5, 2, 3).reshape(3, 5, P, -1)
         res["U" + side] = Ua
         res["G" + side] = Ga if spec.physics == NS else None
     return res
