@@ -36,6 +36,12 @@
 
 namespace mortar {
 
+// Arrays of the register-direct kernel are addressed with 32-bit byte offsets through
+// buffer descriptors: each stays at most kRdMaxBytes (the host checks), so the offset
+// kRdOff of a masked-off lane is beyond every descriptor.  (The VALU kernels' kBufOff,
+// 2 GiB, is inside a flux array of more than 2 GiB, which this kernel accepts.)
+constexpr uint32_t kRdOff = (uint32_t)kRdMaxBytes;
+
 typedef float rd_v4f __attribute__((ext_vector_type(4)));
 typedef double rd_v4d __attribute__((ext_vector_type(4)));
 typedef __bf16 rd_v4bf __attribute__((ext_vector_type(4)));
@@ -299,7 +305,7 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
 
     const int np_ = a.n_par;
     const int nmod = a.nmod;
-    // buffer resources of the arrays (each below 4 GiB; the host checks this)
+    // buffer resources of the arrays (each at most kRdMaxBytes; the host checks this)
     const int pbytes_s = (int)((size_t)P * a.nfs * sizeof(T));
     const int pbytes_m = (int)((size_t)P * a.nfm * sizeof(T));
     const buf_rsrc_t rU_s = buf_rsrc(a.Us, 5u * (uint32_t)pbytes_s);
@@ -343,7 +349,7 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
             const buf_rsrc_t &rs = v < 5 ? rU_s : (v < V ? rG_s : rMet);
             const int pv = v < 5 ? v : (v < V ? v - 5 : v - V);
 #pragma unroll
-            for (int q = 0; q < LF; ++q) ls[v][q] = buf_load<T>(rs, os[q], pv * pbytes_s);
+            for (int q = 0; q < LF; ++q) ls[v][q] = buf_load<T>(rs, os[q], (int)((uint32_t)pv * (uint32_t)pbytes_s));
         }
     };
     auto fetch_m = [&](const TileGeom &g, int cm_) {
@@ -362,7 +368,7 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
             const buf_rsrc_t &rs = v < 5 ? rU_m : rG_m;
             const int pv = v < 5 ? v : v - 5;
 #pragma unroll
-            for (int q = 0; q < LM; ++q) lm[v][q] = buf_load<T>(rs, om[q], pv * pbytes_m);
+            for (int q = 0; q < LM; ++q) lm[v][q] = buf_load<T>(rs, om[q], (int)((uint32_t)pv * (uint32_t)pbytes_m));
         }
     };
     auto proj_s = [&](const T (&b)[LF], acc_t (&d)[RB]) {
@@ -671,11 +677,11 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
                 const int j = Op::row(kq, r);
                 const uint32_t jj = (uint32_t)min(j, NP - 1);
                 const uint32_t o_s = ((line + jj) * (uint32_t)a.nfs + (uint32_t)oc_s) * (uint32_t)sizeof(T) +
-                                     (uint32_t)(v * pbytes_s);
+                                     (uint32_t)v * (uint32_t)pbytes_s;
                 const uint32_t o_m = ((line + jj) * (uint32_t)a.nfm + (uint32_t)oc_m) * (uint32_t)sizeof(T) +
-                                     (uint32_t)(v * pbytes_m);
-                buf_store<T>(T(ds[r]), rF_s, out_s && j < NP ? o_s : kBufOff, 0);
-                buf_store<T>(T(dm[r]), rF_m, out_m && j < NP ? o_m : kBufOff, 0);
+                                     (uint32_t)v * (uint32_t)pbytes_m;
+                buf_store<T>(T(ds[r]), rF_s, out_s && j < NP ? o_s : kRdOff, 0);
+                buf_store<T>(T(dm[r]), rF_m, out_m && j < NP ? o_m : kRdOff, 0);
             }
         }
     }

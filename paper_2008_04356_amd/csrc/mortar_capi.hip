@@ -215,14 +215,14 @@ static bool basis_consts(int N, int node_set, BasisConsts &c)
 // ------------------------------------------------------------------------------------
 
 // The register-direct kernel addresses every input and output array with 32-bit byte
-// offsets: each array must stay below 4 GiB.
+// offsets: each array must stay at most kRdMaxBytes (just below 4 GiB).
 static bool rd_addressable(const mortar_iface_desc &d)
 {
     const int64_t P = (int64_t)(d.N + 1) * (d.N + 1);
     const int64_t elem = d.precision == MORTAR_FP64 ? 8 : 4;
     const int64_t vars = d.physics == MORTAR_NAVIER_STOKES ? 15 : 5;
     const int64_t nf = std::max<int64_t>(d.n_face_static, d.n_face_moving);
-    return vars * P * nf * elem < ((int64_t)1 << 32);
+    return vars * P * nf * elem <= kRdMaxBytes;
 }
 
 // The VALU-projection kernels store through buffer descriptors over one side's five

@@ -108,6 +108,9 @@ hipError_t launch_flux_batched(const Handle &h, const void *const *Us, const voi
 int cons_blocks(int P, int nfaces);
 // Largest flux grid whose workgroups write conservation partials.
 constexpr int kConsGridMax = 4096;
+// Largest array (bytes) the register-direct kernels address with 32-bit buffer offsets;
+// offsets from there up to 4 GiB mark masked-off lanes.
+constexpr int64_t kRdMaxBytes = 0xFFFFFF00;
 hipError_t launch_conservation_final(const Iface &f, double *d_out, hipStream_t st);
 hipError_t launch_conservation(const Iface &f, const void *Fs, const void *Fm, double *d_out,
                                hipStream_t st);

@@ -339,3 +339,61 @@ def test_prepared_stage_equals_separate_calls(M, variant):
             assert torch.equal(ca, cb)
     finally:
         op.close()
+
+
+def test_flux_arrays_beyond_2gib(M):
+    """Size limits: an interface whose state and flux arrays pass 2 GiB (FP64 Euler, N = 9,
+    1024 x 525 faces, 2.0 GiB per array).  The VALU kernels cannot address it, so the
+    default launch takes the MFMA-LDS kernel (64-bit offsets); the register-direct kernel
+    addresses arrays up to just below 4 GiB and masks lanes with an offset beyond that.
+    Both launches agree everywhere (a masked store landing inside the array would show),
+    and the first and last two rows match the oracle on a two-row interface cut from the
+    same data (rows are independent chains along the slide).  Inputs are seeded on the
+    device: a free stream with 1 % uniform perturbations."""
+    import torch
+    N, n_par, n_perp = 9, 1024, 525
+    spec = W.make_plane(N, n_par, n_perp, physics=W.EULER, riemann=W.ROE, precision=W.FP64,
+                        name="beyond-2GiB")
+    assert 5 * spec.P * spec.n_face_static * 8 >= 2 ** 31
+    g = torch.Generator(device="cuda:0").manual_seed(11)
+    rho, vn, p = 1.0, 0.3, 0.71
+    U0 = torch.tensor([rho, rho * vn, 0.0, 0.0, p / 0.4 + 0.5 * rho * vn * vn],
+                      dtype=torch.float64, device="cuda:0")
+
+    def state(nf):
+        r = torch.rand((5, spec.P, nf), generator=g, dtype=torch.float64, device="cuda:0")
+        return U0[:, None, None] + 1e-2 * (2.0 * r - 1.0)
+
+    Us, Um = state(spec.n_face_static), state(spec.n_face_moving)
+    d = 37.3 * spec.l_par
+    n, s = O.decompose(d, spec.l_par)
+    op = M.MortarOperator([spec])
+    try:
+        op.update([d])
+        outs = {}
+        for variant in (None, 2):
+            print(f"[parity] beyond 2 GiB variant {variant}", flush=True)
+            if variant is not None:
+                assert M.mortar_set_tuning(op.h, 0, variant, 0, 0) == 0
+            Fs, Fm = H.alloc_outputs(spec)
+            op.flux([Us], [Um], [None], [None], [Fs], [Fm])
+            torch.cuda.synchronize()
+            outs[variant] = (Fs, Fm)
+        assert op.tuning()[0]["variant"] == 2
+        for k in (0, 1):
+            a, b = outs[None][k], outs[2][k]
+            assert not torch.isnan(a).any() and not torch.isnan(b).any()
+            assert float((a - b).abs().max()) <= 1e-12 * float(a.abs().max())
+        sub = W.make_plane(N, n_par, 2, physics=W.EULER, riemann=W.ROE, precision=W.FP64)
+        sub.dS = spec.dS
+        for r0 in (0, n_perp - 2):
+            cs = torch.from_numpy(spec.face_id_static[r0:r0 + 2].ravel().astype(np.int64)).cuda()
+            cm = torch.from_numpy(spec.face_id_moving[r0:r0 + 2].ravel().astype(np.int64)).cuda()
+            ref = O.mortar_flux(sub, n, s, Us[:, :, cs].cpu().numpy(), Um[:, :, cm].cpu().numpy())
+            for variant, (Fs, Fm) in outs.items():
+                got = (Fs[:, :, cs].cpu().numpy(), Fm[:, :, cm].cpu().numpy())
+                err = H.rel_err(sub, got, ref)
+                print(f"[parity] beyond 2 GiB rows {r0}: variant {variant} err {np.max(err):.2e}", flush=True)
+                assert np.max(err) <= H.TOL[W.FP64], (r0, variant, err)
+    finally:
+        op.close()
