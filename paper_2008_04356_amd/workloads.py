@@ -453,14 +453,14 @@ def round_to(arr, precision: int):
 
 
 # --------------------------------------------------------------------------------------
-# The five workloads
+# The workloads: plane, annulus, turbine-like batch, precision stress, curved shapes
 # --------------------------------------------------------------------------------------
 
 def config(idx: int, precision: int = None):
     """Returns (list of InterfaceSpec, per-stage displacement function(stage) -> list)."""
     if idx == 1:
         spec = make_plane(3, 8, 8, physics=EULER, riemann=LF,
-                          precision=FP64 if precision is None else precision, name="C1")
+                          precision=FP64 if precision is None else precision, name="plane N=3 8x8")
         rng = np.random.Generator(np.random.PCG64(1))
         ns = rng.integers(0, 8, 10)
         ss = rng.uniform(0.0, 1.0, 10)
@@ -470,24 +470,24 @@ def config(idx: int, precision: int = None):
         return [spec], disp
     if idx == 2:
         spec = make_plane(5, 128, 64, physics=NS, riemann=ROE, mu=1e-4,
-                          precision=FP32 if precision is None else precision, name="C2")
+                          precision=FP32 if precision is None else precision, name="plane N=5 128x64")
 
         def disp(k):
             return [0.0137 * k * spec.l_par]
         return [spec], disp
     if idx == 3:
         spec = make_annulus(7, 512, 64, seed=3,
-                            precision=FP32 if precision is None else precision, name="C3")
+                            precision=FP32 if precision is None else precision, name="annulus N=7 512x64")
 
         def disp(k):
             return [0.0137 * k * spec.l_par]
         return [spec], disp
     if idx == 4:
         p = FP32 if precision is None else precision
-        specs = [make_annulus(7, 320, 125, seed=41, precision=p, name="C4-I0"),
-                 make_annulus(5, 256, 72, seed=42, precision=p, name="C4-I1"),
+        specs = [make_annulus(7, 320, 125, seed=41, precision=p, name="annulus N=7 320x125"),
+                 make_annulus(5, 256, 72, seed=42, precision=p, name="annulus N=5 256x72"),
                  make_plane(3, 64, 32, physics=NS, riemann=ROE, mu=1e-4, precision=p,
-                            name="C4-I2")]
+                            name="plane N=3 64x32")]
         speeds = [0.0137, 0.0211, 0.0093]
 
         def disp(k):
@@ -498,14 +498,14 @@ def config(idx: int, precision: int = None):
         # conical with a 30 degree half-angle (7), polynomial face geometry
         spec = make_revolution(7, 512, 64, 0.0 if idx == 6 else math.pi / 6, seed=idx,
                                precision=FP32 if precision is None else precision,
-                               name="cylinder" if idx == 6 else "cone")
+                               name="cylinder N=7 512x64" if idx == 6 else "cone N=7 512x64")
 
         def disp(k):
             return [0.0137 * k * spec.l_par]
         return [spec], disp
     if idx == 5:
         spec = make_plane(9, 256, 256, physics=EULER, riemann=ROE,
-                          precision=FP32 if precision is None else precision, name="C5")
+                          precision=FP32 if precision is None else precision, name="plane N=9 256x256")
 
         def disp(k):
             return [0.0137 * k * spec.l_par]

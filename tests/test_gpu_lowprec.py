@@ -104,7 +104,7 @@ def test_c5_full_size_sampled_rows(M, precision, variant):
         rows = (101, 104)
         ref = H.oracle_flux(spec, oin, n, s, rows=rows)
         err = H.rel_err(spec, (outs[0][0].cpu().numpy(), outs[0][1].cpu().numpy()), ref, rows=rows)
-        print(f"[lowprec] C5 full size {precision}: per-variable error {err}", flush=True)
+        print(f"[lowprec] plane N=9 256x256 full size {precision}: per-variable error {err}", flush=True)
         assert np.max(err) <= 64 * U_ROUND[precision], err
         c = op.conservation([outs[0][0]], [outs[0][1]])[0]
         assert np.all(np.abs(c[:, 0] - c[:, 1]) <= 2e-6 * c[:, 2]), c

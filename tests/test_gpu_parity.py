@@ -270,7 +270,7 @@ def test_turbine_batch_full_size_sampled_rows(M, variant):
             rows = (s.n_perp // 2, s.n_perp // 2 + 2)
             ref = H.oracle_flux(s, H.oracle_inputs(s, inps[i]), n, sf, rows=rows)
             err = H.rel_err(s, (outs[i][0].cpu().numpy(), outs[i][1].cpu().numpy()), ref, rows=rows)
-            print(f"[parity] C4 {s.name} variant {variant}: {err}", flush=True)
+            print(f"[parity] batch {s.name} variant {variant}: {err}", flush=True)
             assert np.max(err) <= H.TOL[W.FP32], (s.name, err)
     finally:
         op.close()
