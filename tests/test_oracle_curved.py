@@ -127,3 +127,35 @@ def test_polynomial_geometry_metrics_close_to_exact():
         assert np.max(np.abs(a.metrics[:3] - b.metrics[:3])) < 1e-8
         assert np.max(np.abs(a.metrics[3] / b.metrics[3] - 1.0)) < 1e-8
         assert np.allclose(np.sum(a.metrics[:3] ** 2, axis=0), 1.0, atol=1e-14)
+
+
+@pytest.mark.parametrize("beta", [0.0, math.pi / 7, math.pi / 2])
+def test_revolution_frame_and_exact_metrics(beta):
+    """The curved-interface inputs themselves: the frame is orthonormal, the normal is
+    perpendicular to the surface's tangents (central differences of the surface point),
+    the exact surface element is |dX/dth x dX/ds| times the reference-face Jacobian, and
+    beta = pi/2 is the flat annulus with normal +e_z."""
+    th = np.linspace(0.1, 6.0, 7)
+    e_th, e_s, n = W.revolution_frame(beta, th)
+    for a in (e_th, e_s, n):
+        assert np.allclose(np.sum(a * a, axis=0), 1.0, atol=1e-15)
+    assert np.allclose(np.sum(e_th * e_s, axis=0), 0.0, atol=1e-15)
+    assert np.allclose(np.sum(e_th * n, axis=0), 0.0, atol=1e-15)
+    assert np.allclose(np.sum(e_s * n, axis=0), 0.0, atol=1e-15)
+    s0, h = 0.23, 1e-6
+    X = lambda t, s: W.revolution_point(beta, 1.0, t, s)  # noqa: E731
+    d_th = (X(th + h, s0) - X(th - h, s0)) / (2 * h)
+    d_s = (X(th, s0 + h) - X(th, s0 - h)) / (2 * h)
+    assert np.allclose(np.sum(d_th * n, axis=0), 0.0, atol=1e-9)
+    assert np.allclose(np.sum(d_s * n, axis=0), 0.0, atol=1e-9)
+    area = np.sqrt(np.sum(np.cross(d_th, d_s, axis=0) ** 2, axis=0))
+    assert np.allclose(area, 1.0 + s0 * math.sin(beta), rtol=1e-8)
+    if beta == math.pi / 2:
+        assert np.allclose(n, np.array([0.0, 0.0, 1.0])[:, None], atol=1e-15)
+    spec = W.make_revolution(3, 10, 2, beta, seed=3, precision=W.FP64, exact_metrics=True)
+    x = W.node_positions(3, W.GAUSS)
+    ds = spec.r_edges[1] - spec.r_edges[0]
+    for pp in range(4):
+        r = 1.0 + (spec.r_edges[0] + 0.5 * (x[pp] + 1.0) * ds) * math.sin(beta)
+        got = spec.metrics[3, 4 * pp, spec.face_id_static[0, 0]]
+        assert abs(got - r * (spec.l_par / 2.0) * (ds / 2.0)) <= 1e-15
