@@ -171,7 +171,12 @@ int mortar_graph_destroy(mortar_graph *g);
  * faces per tile along the sliding direction (0 = the variant's largest; larger values
  * are capped to it).  grid: workgroups of the persistent launch (0 = every resident
  * slot of the device; otherwise at least 8, one per XCD).  Interfaces in one batched
- * launch share the VALU variant and the grid; each has its own tile_len. */
+ * launch share the VALU variant and the grid; each has its own tile_len.
+ * Size limits (per array, bytes): the VALU, wide and hybrid variants need each flux array
+ * below 2 GiB; the register variant needs every state, gradient, metric and flux array
+ * at most 4 GiB - 256; MFMA_LDS has none, and an interface beyond the default variant's
+ * limit is launched with it.  mortar_set_tuning returns INVALID_ARG for a variant that
+ * cannot address the interface. */
 enum { MORTAR_KERNEL_VALU = 0, MORTAR_KERNEL_MFMA_LDS = 1, MORTAR_KERNEL_REGISTER = 2,
        MORTAR_KERNEL_VALU_WIDE = 3, MORTAR_KERNEL_HYBRID = 4 };
 typedef struct mortar_tuning {
