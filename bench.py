@@ -30,13 +30,18 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=300)
     p.add_argument("--warmup", type=int, default=20)
-    p.add_argument("--config", type=int, default=2)
+    p.add_argument("--config", type=int, default=4,
+                   help="workload: 4 = the turbine-like batch of three interfaces (default), "
+                        "2 = plane N=5, 3 = annulus, 5 = plane N=9 Euler, 6/7 = cylinder/cone, 1 = tiny")
     p.add_argument("--no-fp64", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-stages", type=int, default=0,
                    help="oracle stages of the CPU baseline (0: about 15 s of work)")
     p.add_argument("--rotate-bytes", type=float, default=1.2e9)
-    p.add_argument("--graph", action="store_true", help="replay a captured HIP graph per stage")
+    p.add_argument("--graph", action="store_true",
+                   help="replay a captured HIP graph per stage (the default for batches)")
+    p.add_argument("--eager", action="store_true",
+                   help="eager launches per stage, also for batches")
     p.add_argument("--no-autotune", action="store_true",
                    help="launch with the library defaults instead of autotuned launches")
     p.add_argument("--tune-cache", default=None,
@@ -66,7 +71,8 @@ def copy_calibration(mb):
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 5}))
 
 
-TRAFFIC_PROFILES = {2: "profiles/k_mortar_flux_ns_n5_plane128x64_traffic.md"}
+TRAFFIC_PROFILES = {2: "profiles/k_mortar_flux_ns_n5_plane128x64_traffic.md",
+                    4: "profiles/k_mortar_flux_rd_batch_turbine_c4_traffic.md"}
 
 
 def sources_sha256(names):
@@ -80,8 +86,9 @@ def sources_sha256(names):
 
 def measured_traffic(config, precision, tuning):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter
-    summary: its lines "launch variant=V tile_len=T grid=G traffic=BYTES sources=a,b,..
-    sha256=HEX" give the measured traffic of one launch each.  None when there is none for
+    summary: its lines "launch variant=V tile_len=T[,T..] grid=G traffic=BYTES
+    sources=a,b,.. sha256=HEX" give the measured traffic of one launch each (one tile
+    length per interface of the launch).  None when there is none for
     this workload and launch, or the kernel sources have changed since the counters were
     taken."""
     rel = TRAFFIC_PROFILES.get(config)
@@ -95,7 +102,10 @@ def measured_traffic(config, precision, tuning):
             continue
         try:
             kv = dict(x.split("=", 1) for x in line.split()[1:])
-            if any(int(kv[k]) != tuning[0][k] for k in ("variant", "tile_len", "grid")):
+            if any(int(kv[k]) != tuning[0][k] for k in ("variant", "grid")):
+                continue
+            # one tile length per interface of the launch (comma-separated for a batch)
+            if [int(t) for t in kv["tile_len"].split(",")] != [t["tile_len"] for t in tuning]:
                 continue
             if sources_sha256(kv["sources"].split(",")) != kv["sha256"]:
                 return None
@@ -334,46 +344,96 @@ def rel_err_per_var(spec, F_gpu, F_ref):
                   / max(scale[v], floor)) for v in range(5)]
 
 
-def cpu_baseline(M, W, spec, disp, stages, target_s=15.0):
-    """The FP64 oracle as it stands, single thread, on whole-interface stages of the
-    headline interface (inputs as the GPU sees them, promoted to FP64): about target_s
-    seconds of work unless stages is given.  The last stage is also run on the GPU in
-    the headline precision to report the error per output variable."""
+def host_cpu():
+    """Host CPU facts for the baseline: the model name, the processor count the OS
+    reports, the processors this process may run on, and the thread count a pool should
+    use (the affinity count, capped by OMP_NUM_THREADS when that is set)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = os.cpu_count() or 1
+    threads = affinity
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    if omp.isdigit() and int(omp) > 0:
+        threads = min(threads, int(omp))
+    return {"model": model, "nproc": affinity, "os_cpu_count": os.cpu_count(),
+            "threads": max(1, threads)}
+
+
+def cpu_baseline(M, W, specs, disp, stages, target_s=12.0):
+    """The FP64 oracle as it stands on whole stages of the workload (every interface of
+    it; inputs as the GPU sees them, promoted to FP64), timed twice on this host: one
+    thread, then the same routine over row ranges on every usable core (rows are
+    independent periodic chains).  Each leg runs about target_s seconds of work unless
+    stages is given.  The last stage is also run on the GPU in the headline precision to
+    report the error per output variable of each interface."""
     from oracle import oracle as O
     import numpy as np
     import torch
 
-    inp = W.make_inputs(spec, seed=2, delta=disp(1)[0], noise=1e-4)
-    f64 = {k: None if v is None else np.asarray(W.round_to(v, spec.precision), dtype=np.float64)
-           for k, v in inp.items()}
-    t0 = time.perf_counter()
-    k, ref = 0, None
-    while True:
-        k += 1
-        n, s = O.decompose(disp(k)[0], spec.l_par)
-        ref = O.mortar_flux(spec, n, s, f64["Us"], f64["Um"], f64["Gs"], f64["Gm"])
-        el = time.perf_counter() - t0
-        print(f"[bench] oracle stage {k} ({el:.1f} s)", file=sys.stderr, flush=True)
-        if (stages > 0 and k >= stages) or (stages <= 0 and el * (k + 1) / k > target_s):
-            break
-    op = M.MortarOperator([spec])
+    cpu = host_cpu()
+    f64 = []
+    for i, spec in enumerate(specs):
+        inp = W.make_inputs(spec, seed=2 + i, delta=disp(1)[i], noise=1e-4)
+        f64.append({k: None if v is None else np.asarray(W.round_to(v, spec.precision), dtype=np.float64)
+                    for k, v in inp.items()})
+        del inp
+    pts = sum(s.mortar_points for s in specs)
+
+    def leg(threads):
+        t0 = time.perf_counter()
+        k, refs = 0, None
+        while True:
+            k += 1
+            refs = []
+            for i, spec in enumerate(specs):
+                n, s = O.decompose(disp(k)[i], spec.l_par)
+                refs.append(O.mortar_flux(spec, n, s, f64[i]["Us"], f64[i]["Um"], f64[i]["Gs"],
+                                          f64[i]["Gm"], threads=threads))
+            el = time.perf_counter() - t0
+            print(f"[bench] oracle stage {k}, {threads} thread(s) ({el:.1f} s)", file=sys.stderr,
+                  flush=True)
+            if (stages > 0 and k >= stages) or (stages <= 0 and el * (k + 1) / k > target_s):
+                return k, el, refs
+
+    k1, el1, _ = leg(1)
+    kn, eln, refs = leg(cpu["threads"])
+    errs = []
+    op = M.MortarOperator(specs)
     try:
-        dev = {key: None if v is None else torch.from_numpy(np.ascontiguousarray(W.round_to(v, spec.precision))).cuda()
-               for key, v in inp.items()}
-        dt = torch.float64 if spec.precision == W.FP64 else torch.float32
-        Fs = torch.zeros((5, spec.P, spec.n_face_static), dtype=dt, device="cuda")
-        Fm = torch.zeros((5, spec.P, spec.n_face_moving), dtype=dt, device="cuda")
-        op.update([disp(k)[0]])
-        op.flux([dev["Us"]], [dev["Um"]], [dev["Gs"]], [dev["Gm"]], [Fs], [Fm])
+        dev, outs = [], []
+        for i, spec in enumerate(specs):
+            dev.append({key: None if v is None else
+                        torch.from_numpy(np.ascontiguousarray(W.round_to(v, spec.precision))).cuda()
+                        for key, v in f64[i].items()})
+            dt = torch.float64 if spec.precision == W.FP64 else torch.float32
+            outs.append((torch.zeros((5, spec.P, spec.n_face_static), dtype=dt, device="cuda"),
+                         torch.zeros((5, spec.P, spec.n_face_moving), dtype=dt, device="cuda")))
+        op.update(disp(kn))
+        op.flux([d["Us"] for d in dev], [d["Um"] for d in dev], [d["Gs"] for d in dev],
+                [d["Gm"] for d in dev], [o[0] for o in outs], [o[1] for o in outs])
         torch.cuda.synchronize()
-        err = rel_err_per_var(spec, (Fs.double().cpu().numpy(), Fm.double().cpu().numpy()), ref)
+        for spec, o, ref in zip(specs, outs, refs):
+            errs.append(rel_err_per_var(spec, (o[0].double().cpu().numpy(), o[1].double().cpu().numpy()), ref))
     finally:
         op.close()
-    return {"value": k * spec.mortar_points / el, "unit": "mortar points/s", "cores": 1,
+    names = " + ".join(s.name for s in specs)
+    return {"value": kn * pts / eln, "unit": "mortar points/s", "cores": cpu["threads"],
             "kind": "oracle",
-            "sample": f"{k} whole-interface stages of {spec.name} ({spec.mortar_points} mortar "
-                      f"points each; FP64 oracle, one thread, {el:.1f} s)",
-            "gpu_rel_err_per_var": err}
+            "sample": f"{kn} whole stages of {names} ({pts} mortar points per stage; FP64 oracle, "
+                      f"rows split over {cpu['threads']} threads, {eln:.1f} s)",
+            "single_thread": {"value": k1 * pts / el1, "cores": 1,
+                              "sample": f"{k1} whole stages, one thread, {el1:.1f} s"},
+            "host": cpu,
+            "gpu_rel_err_per_var": errs}
 
 
 def main():
@@ -396,8 +456,9 @@ def main():
     torch.cuda.set_device(0)
     prec = {"fp32": W.FP32, "bf16": W.BF16_MFMA, "fp16": W.FP16_MFMA}[a.precision]
     specs32, disp = W.config(a.config, precision=prec)
+    graph = (a.graph or len(specs32) > 1) and not a.eager
     fixed = None if a.tuning is None else tuple(int(x) for x in a.tuning.split(","))
-    r32 = run_leg(M, W, specs32, disp, a.steps, a.warmup, a.rotate_bytes, graph=a.graph,
+    r32 = run_leg(M, W, specs32, disp, a.steps, a.warmup, a.rotate_bytes, graph=graph,
                   tune=not a.no_autotune, tune_cache=a.tune_cache, fixed=fixed,
                   measure_lifting=not a.no_lifting)
     r64 = None
@@ -408,7 +469,7 @@ def main():
                       tune=not a.no_autotune, tune_cache=a.tune_cache)
     cpu = None
     if not a.no_cpu_baseline:
-        cpu = cpu_baseline(M, W, specs32[0], disp, a.cpu_stages)
+        cpu = cpu_baseline(M, W, specs32, disp, a.cpu_stages)
     kargs = {1: "<float,4,Euler,LF>", 2: "<float,6,NS,Roe>", 3: "<float,8,NS+metrics,Roe>",
              4: "<float,NS,Roe,N=3,5,7>", 5: "<float,10,Euler,Roe>",
              6: "<float,8,NS+metrics,Roe>", 7: "<float,8,NS+metrics,Roe>"}
@@ -424,7 +485,7 @@ def main():
                 "per-point metrics, Navier-Stokes Roe+BR1, FP32",
              4: "turbine-like batch: annulus N=7 320x125 + annulus N=5 256x72 + plane N=3 64x32, "
                 "Navier-Stokes Roe+BR1, FP32, one persistent launch per stage"
-                + (" (HIP graph)" if a.graph else ""),
+                + (" (HIP graph)" if graph else ""),
              1: f"plane interface N={spec.N}, {spec.n_par}x{spec.n_perp}, Euler LF, FP32",
              5: f"plane interface N={spec.N}, {spec.n_par}x{spec.n_perp}, Euler Roe, FP32",
              6: f"cylindrical radial interface N={spec.N}, {spec.n_par}x{spec.n_perp} face pairs, "

@@ -69,7 +69,9 @@ enum { MORTAR_FP64 = 0, MORTAR_FP32 = 1, MORTAR_BF16_MFMA = 2, MORTAR_FP16_MFMA 
 /* Description of one sliding interface (Sec. 4.3 index definitions). */
 typedef struct mortar_iface_desc {
     int32_t geometry;         /* MORTAR_GEOM_*: informational; metrics decide the math */
-    int32_t N;                /* polynomial degree, 1 <= N <= 9 */
+    int32_t N;                /* polynomial degree, 1 <= N <= 15; N >= 10: FP64/FP32 only,
+                                 VALU-projection kernel only, one launch per interface,
+                                 flux arrays below 2 GiB (else UNSUPPORTED) */
     int32_t node_set;         /* MORTAR_NODES_*: Gauss or Gauss-Lobatto (Sec. 3.1) */
     int32_t n_par;            /* faces per side along the sliding direction (periodic) */
     int32_t n_perp;           /* faces per side across it */
@@ -175,8 +177,8 @@ int mortar_graph_destroy(mortar_graph *g);
  * Size limits (per array, bytes): the VALU, wide and hybrid variants need each flux array
  * below 2 GiB; the register variant needs every state, gradient, metric and flux array
  * at most 4 GiB - 256; MFMA_LDS has none, and an interface beyond the default variant's
- * limit is launched with it.  mortar_set_tuning returns INVALID_ARG for a variant that
- * cannot address the interface. */
+ * limit is launched with it.  Degrees N >= 10 have only MORTAR_KERNEL_VALU.
+ * mortar_set_tuning returns INVALID_ARG for a variant that cannot address the interface. */
 enum { MORTAR_KERNEL_VALU = 0, MORTAR_KERNEL_MFMA_LDS = 1, MORTAR_KERNEL_REGISTER = 2,
        MORTAR_KERNEL_VALU_WIDE = 3, MORTAR_KERNEL_HYBRID = 4 };
 typedef struct mortar_tuning {
@@ -226,6 +228,13 @@ int mortar_get_displacement(mortar_handle *h, int iface, int64_t *n, double *s);
  * [2][n_face] with m[i_sub][i_face] = i_mortar, -1 for columns not on the interface)
  * of one side (0 = static, 1 = moving), Sec. 4.4 and Appendix A. */
 int mortar_get_index_map(mortar_handle *h, int iface, int side, int32_t *A, int32_t *m);
+
+/* Static-to-moving pairing of the current displacement (Sec. 4.3, index relation
+ * i~ = (i - n + i_sub - 1) mod n_par, 0-based, periodic): pair (host [2][n_par], caller
+ * owned) gets pair[i_sub * n_par + i_par] = the moving face index along the slide that
+ * mortar (i_par, i_sub) lies on, the same in every row.  Evaluated on the device by the
+ * routine the index map is built from.  Synchronizes the device. */
+int mortar_get_pairing(mortar_handle *h, int iface, int32_t *pair);
 
 /* FP64 projection matrices of the current s: Pf[4][NP][NP] (mortar node, face node) and
  * Pb[4][NP][NP] (face node, mortar node); order: static i_sub 0, static i_sub 1, moving

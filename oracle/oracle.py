@@ -192,9 +192,12 @@ def _iface(spec):
     return keep
 
 
-def mortar_flux(spec, n: int, s: float, Us, Um, Gs=None, Gm=None, rows=None):
+def mortar_flux(spec, n: int, s: float, Us, Um, Gs=None, Gm=None, rows=None, threads=1):
     """Whole operator (FP64).  Us/Um: [5][P][n_face], Gs/Gm: [3][5][P][n_face] or None.
-    rows=(r0, r1) restricts the work to those rows (other columns of the outputs are 0)."""
+    rows=(r0, r1) restricts the work to those rows (other columns of the outputs are 0).
+    threads > 1 splits the rows into that many contiguous ranges and runs the same C
+    routine on each range in its own thread (rows are independent periodic chains and
+    write disjoint face columns; ctypes releases the GIL during the call)."""
     P = (spec.N + 1) ** 2
     Us, Um = _f64(Us), _f64(Um)
     Fs = np.zeros((5, P, spec.n_face_static))
@@ -203,16 +206,28 @@ def mortar_flux(spec, n: int, s: float, Us, Um, Gs=None, Gm=None, rows=None):
     gs = _f64(Gs) if Gs is not None else None
     gm = _f64(Gm) if Gm is not None else None
     r0, r1 = (0, spec.n_perp) if rows is None else rows
-    rc = lib().orc_mortar_flux(C.byref(keep.st), n, s, _d(Us), _d(Um),
-                               _d(gs) if gs is not None else None,
-                               _d(gm) if gm is not None else None,
-                               _d(Fs), _d(Fm), r0, r1)
-    if rc:
-        raise RuntimeError(f"oracle mortar_flux failed ({rc})")
+
+    def run(a, b):
+        return lib().orc_mortar_flux(C.byref(keep.st), n, s, _d(Us), _d(Um),
+                                     _d(gs) if gs is not None else None,
+                                     _d(gm) if gm is not None else None,
+                                     _d(Fs), _d(Fm), a, b)
+
+    threads = max(1, min(int(threads), r1 - r0))
+    if threads == 1:
+        rcs = [run(r0, r1)]
+    else:
+        from concurrent.futures import ThreadPoolExecutor
+        cuts = [r0 + (r1 - r0) * k // threads for k in range(threads + 1)]
+        with ThreadPoolExecutor(threads) as ex:
+            rcs = list(ex.map(run, cuts[:-1], cuts[1:]))
+    for rc in rcs:
+        if rc:
+            raise RuntimeError(f"oracle mortar_flux failed ({rc})")
     return Fs, Fm
 
 
-def mortar_lifting(spec, n: int, s: float, Us, Um, rows=None):
+def mortar_lifting(spec, n: int, s: float, Us, Um, rows=None, threads=1):
     """BR1 lifting surface term through the same operator (FP64): for each normal
     component d the mean of both mortar states times n_d dS, projected back onto both
     sides.  Returns Ls, Lm of shape [3][5][P][n_face]."""
@@ -221,7 +236,7 @@ def mortar_lifting(spec, n: int, s: float, Us, Um, rows=None):
     for d in range(3):
         sp = copy.copy(spec)
         sp.physics, sp.riemann = EULER, LIFT + d
-        comp.append(mortar_flux(sp, n, s, Us, Um, rows=rows))
+        comp.append(mortar_flux(sp, n, s, Us, Um, rows=rows, threads=threads))
     return np.stack([c[0] for c in comp]), np.stack([c[1] for c in comp])
 
 

@@ -1,12 +1,14 @@
 // Launch, occupancy and tile-capacity helpers of the VALU flux kernel for one element
-// type and one LDS budget; each instantiation unit exports them under its own names.
+// type, one LDS budget and a range of degrees; each instantiation unit exports them under
+// its own names.
 #pragma once
 
 #include "k_flux.h"
 
 namespace mortar {
 
-template <typename T, int BUDGET>
+// Instantiations for NP in [LO, HI].
+template <typename T, int BUDGET, int LO = 2, int HI = kMaxNFast + 1>
 struct ValuLaunch {
     template <int NP, bool NSV, bool MET, int RIEM>
     static hipError_t go(const FluxArgs<T> &a, int grid, hipStream_t st)
@@ -56,36 +58,23 @@ struct ValuLaunch {
         return met ? FluxCfg<T, NP, false, true, BUDGET>::TF : FluxCfg<T, NP, false, false, BUDGET>::TF;
     }
 
-#define MORTAR_VALU_NP_SWITCH(EXPR, DEFAULT)                                            \
-    switch (NP) {                                                                       \
-    case 2: return EXPR(2); case 3: return EXPR(3); case 4: return EXPR(4);            \
-    case 5: return EXPR(5); case 6: return EXPR(6); case 7: return EXPR(7);            \
-    case 8: return EXPR(8); case 9: return EXPR(9); case 10: return EXPR(10);          \
-    default: return DEFAULT;                                                            \
-    }
-
     static int occupancy(int NP, bool ns, bool met, int riem)
     {
-#define E(np) occ<np>(ns, met, riem)
-        MORTAR_VALU_NP_SWITCH(E, 1)
-#undef E
+        return np_dispatch<LO, HI, int>(NP, 1, [&](auto c) { return occ<decltype(c)::value>(ns, met, riem); });
     }
 
     static int capacity(int NP, bool ns, bool met)
     {
-#define E(np) cap<np>(ns, met)
-        MORTAR_VALU_NP_SWITCH(E, 0)
-#undef E
+        return np_dispatch<LO, HI, int>(NP, 0, [&](auto c) { return cap<decltype(c)::value>(ns, met); });
     }
 
     static hipError_t launch(const FluxArgs<T> &a, int NP, int grid, bool ns, bool met, int riem,
                              hipStream_t st)
     {
-#define E(np) pick<np>(a, grid, ns, met, riem, st)
-        MORTAR_VALU_NP_SWITCH(E, hipErrorInvalidValue)
-#undef E
+        return np_dispatch<LO, HI, hipError_t>(NP, hipErrorInvalidValue, [&](auto c) {
+            return pick<decltype(c)::value>(a, grid, ns, met, riem, st);
+        });
     }
-#undef MORTAR_VALU_NP_SWITCH
 };
 
 }  // namespace mortar

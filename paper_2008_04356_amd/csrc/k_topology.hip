@@ -36,10 +36,32 @@ hipError_t launch_assemble(const Iface &f, hipStream_t st)
     switch (f.NP) {
         MORTAR_ASM_CASE(2) MORTAR_ASM_CASE(3) MORTAR_ASM_CASE(4) MORTAR_ASM_CASE(5)
         MORTAR_ASM_CASE(6) MORTAR_ASM_CASE(7) MORTAR_ASM_CASE(8) MORTAR_ASM_CASE(9)
-        MORTAR_ASM_CASE(10)
+        MORTAR_ASM_CASE(10) MORTAR_ASM_CASE(11) MORTAR_ASM_CASE(12) MORTAR_ASM_CASE(13)
+        MORTAR_ASM_CASE(14) MORTAR_ASM_CASE(15) MORTAR_ASM_CASE(16)
     default: return hipErrorInvalidValue;
     }
 #undef MORTAR_ASM_CASE
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------
+// Pairing of every mortar of a row with its moving face, for inspection: the index
+// relation the index map is built from, evaluated on the device for the current n.
+// ------------------------------------------------------------------------------------
+
+__global__ void k_pairing(int n_par, int nmod, int32_t *__restrict__ pair)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < 2 * n_par) pair[t] = moving_partner(t % n_par, t / n_par, nmod, n_par);
+}
+
+hipError_t launch_pairing(const Iface &f, hipStream_t st)
+{
+    const int64_t np = f.d.n_par;
+    const int nmod = (int)(((f.n % np) + np) % np);
+    const int total = 2 * f.d.n_par;
+    hipLaunchKernelGGL(k_pairing, dim3((total + 255) / 256), dim3(256), 0, st, f.d.n_par, nmod,
+                       f.d_pair);
     return hipGetLastError();
 }
 
@@ -68,9 +90,7 @@ __device__ static inline void map_element(const MapArgs &a, int e, int &ia, int 
     const int r = e >> 1;
     ia = r / a.n_perp;
     ip = r - ia * a.n_perp;
-    int jt = ia - a.nmod + k - 1;          // moving index of the mortar (index relation)
-    jt %= a.n_par;
-    if (jt < 0) jt += a.n_par;
+    const int jt = moving_partner(ia, k, a.nmod, a.n_par);   // moving face of the mortar
     if (a.side == 0) {                     // static side: owner of the moving face
         oid = a.oid_opp[ip * a.n_par + jt];
         col = a.fid[ip * a.n_par + ia];

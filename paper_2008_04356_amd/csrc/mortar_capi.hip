@@ -126,10 +126,14 @@ static bool gauss_nodes(int np, double *x, double *w)
     if ((int)r.size() != np) return false;
     for (int i = 0; i < np; ++i) {
         x[i] = r[i];
-        // w = 2 (1 - x^2) / (n P_{n-1}(x))^2  for roots of P_n
+        // w = 2 / ((1 - x^2) P_n'(x)^2) with P_n' = n (P_{n-1} - x P_n) / (1 - x^2); the
+        // x P_n term (P_n is only zero up to rounding at the computed root) keeps the
+        // weights accurate to a few ulps at the higher degrees
         double pn, pn1;
         legendre_pair(np, r[i], pn, pn1);
-        w[i] = 2.0 * (1.0 - r[i] * r[i]) / ((np * pn1) * (np * pn1));
+        const double omx2 = (1.0 - r[i]) * (1.0 + r[i]);
+        const double dp = np * (pn1 - r[i] * pn) / omx2;
+        w[i] = 2.0 / (omx2 * dp * dp);
     }
     return true;
 }
@@ -244,8 +248,12 @@ static int validate_one(const mortar_iface_desc &d)
     if (d.physics != MORTAR_EULER && d.physics != MORTAR_NAVIER_STOKES) return MORTAR_ERR_INVALID_ARG;
     if (d.riemann != MORTAR_FLUX_LF && d.riemann != MORTAR_FLUX_ROE) return MORTAR_ERR_INVALID_ARG;
     if (d.precision < MORTAR_FP64 || d.precision > MORTAR_FP16_MFMA) return MORTAR_ERR_INVALID_ARG;
-    if ((d.precision == MORTAR_BF16_MFMA || d.precision == MORTAR_FP16_MFMA) && !rd_addressable(d))
+    if ((d.precision == MORTAR_BF16_MFMA || d.precision == MORTAR_FP16_MFMA) &&
+        (!rd_addressable(d) || d.N > kMaxNFast))
         return MORTAR_ERR_UNSUPPORTED;
+    // above kMaxNFast only the VALU-projection kernel exists: its flux arrays must stay
+    // below 2 GiB
+    if (d.N > kMaxNFast && !valu_addressable(d)) return MORTAR_ERR_UNSUPPORTED;
     const int64_t F = (int64_t)d.n_par * d.n_perp;
     if (F > (int64_t)1 << 28) return MORTAR_ERR_UNSUPPORTED;
     if (d.n_face_static < F || d.n_face_moving < F) return MORTAR_ERR_INVALID_ARG;
@@ -288,7 +296,7 @@ static void free_iface(Iface &f)
 {
     void *bufs[] = {f.d_fid_s, f.d_fid_m, f.d_oid_s, f.d_oid_m, f.d_oval_s, f.d_oval_m,
                     f.d_metrics, f.d_params, f.d_basis, f.d_A[0], f.d_A[1], f.d_m[0],
-                    f.d_m[1], f.d_hist, f.d_cons, f.d_cons_out, f.d_cons_wg};
+                    f.d_m[1], f.d_hist, f.d_pair, f.d_cons, f.d_cons_out, f.d_cons_wg};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     f = Iface();
@@ -342,6 +350,7 @@ static int variant_occupancy(const Iface &f, int variant)
 static bool variant_allowed(const Iface &f, int variant)
 {
     if (variant < 0 || variant > 4) return false;
+    if (f.d.N > kMaxNFast) return variant == 0 && valu_addressable(f.d);
     if (f.lp) return variant == 2;
     if (variant == 4)
         return f.elem == 4 && valu_addressable(f.d) &&
@@ -396,6 +405,8 @@ static int setup_one(const mortar_iface_desc &d, Iface &f)
             hipMalloc((void **)&f.d_m[s], sizeof(int32_t) * 2 * (size_t)nf) != hipSuccess)
             return MORTAR_ERR_OOM;
     }
+    if (hipMalloc((void **)&f.d_pair, sizeof(int32_t) * 2 * (size_t)d.n_par) != hipSuccess)
+        return MORTAR_ERR_OOM;
     f.n_sort_blocks = (2 * f.F + kSortBlock - 1) / kSortBlock;
     const int R = std::max(f.R_s, f.R_m);
     if (hipMalloc((void **)&f.d_hist, sizeof(int32_t) * (size_t)R * f.n_sort_blocks) != hipSuccess)
@@ -572,7 +583,7 @@ int mortar_setup(const mortar_iface_desc *desc, int n_iface, mortar_handle **out
         bool same = true, turbine = true;
         for (const Iface &f : h->ifs) {
             same = same && f.elem == f0.elem && f.d.physics == f0.d.physics &&
-                   f.d.riemann == f0.d.riemann && f.flux_variant == 0;
+                   f.d.riemann == f0.d.riemann && f.flux_variant == 0 && f.d.N <= kMaxNFast;
             turbine = turbine && (f.NP == 4 || f.NP == 6 || f.NP == 8);
         }
         const bool ns = f0.d.physics == MORTAR_NAVIER_STOKES;
@@ -706,6 +717,18 @@ int mortar_get_index_map(mortar_handle *h, int iface, int side, int32_t *A, int3
     if (A) TRY_HIP(hipMemcpy(A, f.d_A[side], sizeof(int32_t) * 10 * (size_t)f.F, hipMemcpyDeviceToHost));
     const int nf = side ? f.d.n_face_moving : f.d.n_face_static;
     if (m) TRY_HIP(hipMemcpy(m, f.d_m[side], sizeof(int32_t) * 2 * (size_t)nf, hipMemcpyDeviceToHost));
+    return MORTAR_OK;
+}
+
+int mortar_get_pairing(mortar_handle *h, int iface, int32_t *pair)
+{
+    if (!h || iface < 0 || iface >= (int)h->ifs.size() || !pair) return MORTAR_ERR_INVALID_ARG;
+    const Iface &f = h->ifs[iface];
+    if (!f.ready) return MORTAR_ERR_NOT_READY;
+    TRY_HIP(hipDeviceSynchronize());
+    TRY_HIP(launch_pairing(f, nullptr));
+    TRY_HIP(hipDeviceSynchronize());
+    TRY_HIP(hipMemcpy(pair, f.d_pair, sizeof(int32_t) * 2 * (size_t)f.d.n_par, hipMemcpyDeviceToHost));
     return MORTAR_OK;
 }
 

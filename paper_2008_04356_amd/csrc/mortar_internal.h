@@ -4,16 +4,44 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 #include <vector>
 
 #include "mortar.h"
 
 namespace mortar {
 
-constexpr int kMaxN = 9;
+constexpr int kMaxN = 15;
 constexpr int kMaxNP = kMaxN + 1;
+// Degrees up to kMaxNFast (NP <= 10) have every kernel variant, batching and the bf16/fp16
+// modes; higher degrees run the VALU-projection kernel, one launch per interface.
+constexpr int kMaxNFast = 9;
 constexpr int kMaxOwners = 1024;   // distinct owner ranks per side (index-map sort keys)
 constexpr int kSortBlock = 256;    // elements per block of the index-map counting sort
+
+// Static-to-moving pairing (Sec. 4.3, index relation): mortar (i_par, i_sub) of a row lies
+// on the moving face (i_par - n + i_sub - 1) mod n_par of the same row; nmod = n mod
+// n_par in [0, n_par).  0-based indices, periodic wrap along the slide.
+__host__ __device__ inline int moving_partner(int i_par, int i_sub, int nmod, int n_par)
+{
+    int j = (i_par - nmod + i_sub - 1) % n_par;   // in (-n_par, n_par)
+    return j < 0 ? j + n_par : j;
+}
+
+// Run-time NP -> compile-time instantiation: f(std::integral_constant<int, NP>) for NP in
+// [LO, HI], dflt otherwise.
+template <int LO, int HI, typename R, typename F>
+inline R np_dispatch(int NP, R dflt, F &&f)
+{
+    if constexpr (LO > HI) {
+        (void)NP;
+        (void)f;
+        return dflt;
+    } else {
+        if (NP == LO) return f(std::integral_constant<int, LO>{});
+        return np_dispatch<LO + 1, HI, R>(NP, dflt, f);
+    }
+}
 
 // Per-interface device parameter block, rewritten by the assembly kernel every stage.
 // Header followed by matrices: double Pf[4][NP][NP], double Pb[4][NP][NP],
@@ -62,6 +90,7 @@ struct Iface {
     int32_t *d_A[2] = {nullptr, nullptr};  // [5][2F] per side
     int32_t *d_m[2] = {nullptr, nullptr};  // [2][n_face] per side
     int32_t *d_hist = nullptr;             // [R][n_sort_blocks] counting-sort scratch
+    int32_t *d_pair = nullptr;             // [2][n_par] pairing, written by mortar_get_pairing
     int n_sort_blocks = 0;
     int64_t n = 0;
     double s = 0.0;
@@ -99,6 +128,7 @@ struct Handle {
 // ---- launchers (kernels in k_*.hip) ------------------------------------------------
 hipError_t launch_assemble(const Iface &f, hipStream_t st);
 hipError_t launch_index_map(Iface &f, int side, hipStream_t st);
+hipError_t launch_pairing(const Iface &f, hipStream_t st);
 hipError_t launch_flux(const Iface &f, int n_cu, const void *Us, const void *Um, const void *Gs,
                        const void *Gm, void *Fs, void *Fm, hipStream_t st);
 struct Handle;

@@ -73,6 +73,7 @@ def _load():
     L.mortar_get_displacement.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int64), _dp]
     L.mortar_get_index_map.argtypes = [C.c_void_p, C.c_int, C.c_int, _ip, _ip]
     L.mortar_get_projection.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
+    L.mortar_get_pairing.argtypes = [C.c_void_p, C.c_int, _ip]
     L.mortar_conservation.argtypes = [C.c_void_p, _vpp, _vpp, _dp, C.c_void_p]
     L.mortar_conservation_device.argtypes = [C.c_void_p, _vpp, _vpp, C.c_void_p, C.c_void_p]
     L.mortar_graph_create.argtypes = [C.c_void_p, _vpp, _vpp, _vpp, _vpp, _vpp, _vpp,
@@ -349,6 +350,12 @@ class MortarOperator:
         _check(lib.mortar_get_index_map(self.h, iface, side, A.ctypes.data_as(_ip),
                                         m.ctypes.data_as(_ip)), "mortar_get_index_map")
         return A, m
+
+    def pairing(self, iface=0):
+        """[2][n_par] int32: moving face index of mortar (i_par, i_sub) in every row."""
+        pair = np.zeros((2, self.specs[iface].n_par), dtype=np.int32)
+        _check(lib.mortar_get_pairing(self.h, iface, pair.ctypes.data_as(_ip)), "mortar_get_pairing")
+        return pair
 
     def projection(self, iface=0):
         NP = self.specs[iface].N + 1

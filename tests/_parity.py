@@ -53,8 +53,19 @@ def gpu_flux(op, specs, dins, outs=None):
     return outs
 
 
+def oracle_threads():
+    """Threads for the oracle's row ranges: the usable cores, at most 16."""
+    import os
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
 def oracle_flux(spec, oin, n, s, rows=None):
-    return O.mortar_flux(spec, n, s, oin["Us"], oin["Um"], oin["Gs"], oin["Gm"], rows=rows)
+    return O.mortar_flux(spec, n, s, oin["Us"], oin["Um"], oin["Gs"], oin["Gm"], rows=rows,
+                         threads=oracle_threads())
 
 
 def rel_err(spec, F_gpu, F_ref, rows=None):

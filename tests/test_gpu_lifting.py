@@ -1,7 +1,7 @@
 """GPU: the BR1 lifting surface term (mortar_lifting) against the FP64 oracle, element
 by element per output plane (3 normal components x 5 variables), at sizes that span
-several tiles and a ragged tail, with per-point metrics, over degrees, and the
-benchmark workload's shape at full size on sampled rows."""
+several tiles and a ragged tail, with per-point metrics, over degrees 1-15, and the
+plane N=5 workload's shape at full size, every row."""
 import numpy as np
 import pytest
 
@@ -60,7 +60,7 @@ def _case(M, spec, disps, seed=3, noise=1e-3, rows=None):
             op.lifting([din["Us"]], [din["Um"]], [Ls], [Lm])
             torch.cuda.synchronize()
             got = (Ls.cpu().numpy(), Lm.cpu().numpy())
-            ref = O.mortar_lifting(spec, n, s, oin["Us"], oin["Um"], rows=rows)
+            ref = O.mortar_lifting(spec, n, s, oin["Us"], oin["Um"], rows=rows, threads=H.oracle_threads())
             err = _err(spec, got, ref, rows=rows)
             assert np.max(err) <= H.TOL[spec.precision], (d, err)
             for L, fid, nf in ((got[0], spec.face_id_static, spec.n_face_static),
@@ -86,16 +86,17 @@ def test_annulus_metrics(M, precision):
 
 
 @pytest.mark.parametrize("N,node_set", [(1, W.GAUSS), (2, W.LGL), (3, W.GAUSS), (4, W.LGL),
-                                        (6, W.GAUSS), (8, W.LGL), (9, W.GAUSS)])
+                                        (6, W.GAUSS), (8, W.LGL), (9, W.GAUSS), (10, W.GAUSS),
+                                        (12, W.LGL), (15, W.GAUSS)])
 def test_degrees(M, N, node_set):
     spec = W.make_plane(N, 23, 2, physics=W.EULER, riemann=W.ROE, node_set=node_set,
                         precision=W.FP32, scramble_seed=N, extra_cols=1)
     _case(M, spec, [0.41 * spec.l_par, 5.003 * spec.l_par], seed=N)
 
 
-def test_benchmark_workload_full_size_sampled_rows(M):
+def test_plane_workload_full_size_all_rows(M):
     specs, disp = W.config(2, precision=W.FP32)
-    _case(M, specs[0], [disp(137)[0]], seed=2, noise=1e-4, rows=(5, 8))
+    _case(M, specs[0], [disp(137)[0]], seed=2, noise=1e-4)
 
 
 def test_not_ready_before_update(M):

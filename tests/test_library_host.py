@@ -68,7 +68,12 @@ def _desc(M, **kw):
 def test_validation_errors_without_gpu(M):
     assert M.mortar_validate([_desc(M)]) == M.OK
     assert M.mortar_validate([_desc(M, N=0)]) == M.ERR_INVALID_ARG
-    assert M.mortar_validate([_desc(M, N=12)]) == M.ERR_UNSUPPORTED
+    assert M.mortar_validate([_desc(M, N=12)]) == M.OK
+    assert M.mortar_validate([_desc(M, N=15)]) == M.OK
+    assert M.mortar_validate([_desc(M, N=16)]) == M.ERR_UNSUPPORTED
+    # degrees above 9: no bf16/fp16 projection modes
+    assert M.mortar_validate([_desc(M, N=10, precision=M.BF16_MFMA)]) == M.ERR_UNSUPPORTED
+    assert M.mortar_validate([_desc(M, N=9, precision=M.BF16_MFMA)]) == M.OK
     assert M.mortar_validate([_desc(M, n_par=0)]) == M.ERR_INVALID_ARG
     assert M.mortar_validate([_desc(M, physics=7)]) == M.ERR_INVALID_ARG
     assert M.mortar_validate([_desc(M, riemann=3)]) == M.ERR_INVALID_ARG
@@ -95,7 +100,7 @@ def test_validation_errors_without_gpu(M):
 def test_library_node_sets(M, node_set):
     """The library's own node routine (bracketing + bisection) against the oracle's
     (Newton) and numpy's, for every supported degree."""
-    for N in range(1, 10):
+    for N in range(1, 16):
         x, w = M.mortar_basis(N, node_set)
         xo, wo = O.nodes(N, node_set)
         assert np.max(np.abs(x - xo)) < 4e-16 and np.max(np.abs(w - wo)) < 4e-15
@@ -103,6 +108,6 @@ def test_library_node_sets(M, node_set):
             xn, wn = np.polynomial.legendre.leggauss(N + 1)
             assert np.max(np.abs(x - xn)) < 4e-16
     with pytest.raises(M.MortarError):
-        M.mortar_basis(10, node_set)
+        M.mortar_basis(16, node_set)
     with pytest.raises(M.MortarError):
         M.mortar_basis(0, node_set)

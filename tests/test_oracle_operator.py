@@ -289,3 +289,16 @@ def test_static_metrics_are_interpolated_along_the_slide(node_set):
     Fs, Fm = O.mortar_flux(spec, 2, 0.29, inp["Us"], inp["Um"])
     ref = inp["Us"] * met[3][None]
     assert np.max(np.abs(Fs - ref)) < 1e-13
+
+
+def test_row_threads_give_the_same_bits():
+    """The all-core form of the oracle (row ranges in threads) writes exactly the values
+    of the single-thread run: rows are independent chains with disjoint face columns."""
+    spec = W.make_plane(4, 13, 7, physics=W.NS, riemann=W.ROE, mu=1e-3, precision=W.FP64,
+                        scramble_seed=3, extra_cols=2)
+    inp = W.make_inputs(spec, seed=3, delta=2.71 * spec.l_par, noise=1e-3)
+    n, s = O.decompose(2.71 * spec.l_par, spec.l_par)
+    one = O.mortar_flux(spec, n, s, inp["Us"], inp["Um"], inp["Gs"], inp["Gm"])
+    for t in (2, 3, 7, 16):
+        many = O.mortar_flux(spec, n, s, inp["Us"], inp["Um"], inp["Gs"], inp["Gm"], threads=t)
+        assert np.array_equal(one[0], many[0]) and np.array_equal(one[1], many[1])
