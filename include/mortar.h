@@ -193,8 +193,13 @@ typedef struct mortar_tuning {
  * launches per candidate after one warm-up, and keeps the fastest.  Candidates: each
  * applicable variant with three tile lengths (single-interface launches), or three tile
  * lengths per interface and the grid (batched launch).  Needs a displacement already
- * set; synchronizes stream; allocates nothing on the device.  Graphs captured before a
- * tuning change are refused by mortar_graph_launch (UNSUPPORTED): capture them again. */
+ * set; synchronizes stream.  Allocates one 512 MiB device buffer for the duration of the
+ * call and frees it before returning: it is filled before every timed launch so that the
+ * inputs come from HBM (a stage with fresh data does not find them in the caches); if
+ * that allocation fails the candidates are timed with warm caches.  A HIP error during
+ * the timing returns HIP_ERROR with the handle's previous tuning restored.  Graphs
+ * captured before a tuning change are refused by mortar_graph_launch (UNSUPPORTED):
+ * capture them again. */
 int mortar_autotune(mortar_handle *h, const void *const *U_s, const void *const *U_m,
                     const void *const *G_s, const void *const *G_m, void *const *F_s,
                     void *const *F_m, int reps, void *stream);

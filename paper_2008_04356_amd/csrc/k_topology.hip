@@ -347,21 +347,29 @@ hipError_t launch_conservation_final(const Iface &f, double *d_out, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t launch_conservation(const Iface &f, const void *Fs, const void *Fm, double *d_out,
-                               hipStream_t st)
+// The pass over the flux arrays and the final reduction, with the partials in part
+// (10 groups x cons_blocks() x 2 doubles).
+static hipError_t launch_conservation_into(const Iface &f, const void *Fs, const void *Fm,
+                                           double *part, double *d_out, hipStream_t st)
 {
     const dim3 grid(cons_face_blocks(f.F), 10);
     const int nb = (int)grid.x;
     if (f.d.precision == MORTAR_FP64)
         hipLaunchKernelGGL(k_cons_partial<double>, grid, dim3(256), 0, st,
                            (const double *)Fs, (const double *)Fm, f.d_fid_s, f.d_fid_m,
-                           f.d_basis, f.NP, f.F, f.d.n_face_static, f.d.n_face_moving, f.d_cons);
+                           f.d_basis, f.NP, f.F, f.d.n_face_static, f.d.n_face_moving, part);
     else
         hipLaunchKernelGGL(k_cons_partial<float>, grid, dim3(256), 0, st,
                            (const float *)Fs, (const float *)Fm, f.d_fid_s, f.d_fid_m,
-                           f.d_basis, f.NP, f.F, f.d.n_face_static, f.d.n_face_moving, f.d_cons);
-    hipLaunchKernelGGL(k_cons_final, dim3(1), dim3(640), 0, st, f.d_cons, nb, d_out);
+                           f.d_basis, f.NP, f.F, f.d.n_face_static, f.d.n_face_moving, part);
+    hipLaunchKernelGGL(k_cons_final, dim3(1), dim3(640), 0, st, part, nb, d_out);
     return hipGetLastError();
+}
+
+hipError_t launch_conservation(const Iface &f, const void *Fs, const void *Fm, double *d_out,
+                               hipStream_t st)
+{
+    return launch_conservation_into(f, Fs, Fm, f.d_cons, d_out, st);
 }
 
 }  // namespace mortar

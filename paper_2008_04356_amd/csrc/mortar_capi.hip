@@ -823,6 +823,9 @@ int mortar_graph_create(mortar_handle *h, const void *const *U_s, const void *co
     if (rc == MORTAR_OK && hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess)
         rc = MORTAR_ERR_HIP;
     if (cs) (void)hipStreamDestroy(cs);
+    // the captured launch has not run: no partials of it exist until a replay writes them
+    // (mortar_graph_launch records them per replay)
+    for (auto &f : h->ifs) f.cons_nb = 0;
     if (rc != MORTAR_OK) {
         mortar_graph_destroy(g);
         return rc;
@@ -972,6 +975,10 @@ static int vmax_tile(const Iface &f, int variant)
     return f.elem == 8 ? flux_tile_capacity_f64(f.NP, ns, met) : flux_tile_capacity_f32(f.NP, ns, met);
 }
 
+static int autotune_run(mortar_handle *h, const void *const *U_s, const void *const *U_m,
+                        const void *const *G_s, const void *const *G_m, void *const *F_s,
+                        void *const *F_m, int reps, hipStream_t st);
+
 extern "C" {
 
 int mortar_autotune(mortar_handle *h, const void *const *U_s, const void *const *U_m,
@@ -989,6 +996,62 @@ int mortar_autotune(mortar_handle *h, const void *const *U_s, const void *const 
         if (!U_s[i] || !U_m[i] || !F_s[i] || !F_m[i]) return MORTAR_ERR_INVALID_ARG;
         if (ns && (!G_s || !G_m || !G_s[i] || !G_m[i])) return MORTAR_ERR_INVALID_ARG;
     }
+    const int rc = autotune_run(h, U_s, U_m, G_s, G_m, F_s, F_m, reps, st);
+    return rc;
+}
+
+}  // extern "C"
+
+// The tuning state of a handle, saved before the autotuner times its candidates and put
+// back when a HIP error ends it early (the handle then launches as before the call).
+struct TuningState {
+    int batch_variant, tune_grid_batch;
+    unsigned epoch;
+    std::vector<int> variant, occ, tile, grid;
+    explicit TuningState(const Handle &h)
+        : batch_variant(h.batch_variant), tune_grid_batch(h.tune_grid_batch), epoch(h.tune_epoch)
+    {
+        for (const Iface &f : h.ifs) {
+            variant.push_back(f.flux_variant);
+            occ.push_back(f.flux_occ);
+            tile.push_back(f.tune_tile);
+            grid.push_back(f.tune_grid);
+        }
+    }
+    void restore(Handle &h) const
+    {
+        h.batch_variant = batch_variant;
+        h.tune_grid_batch = tune_grid_batch;
+        h.tune_epoch = epoch;
+        for (size_t i = 0; i < h.ifs.size(); ++i) {
+            h.ifs[i].flux_variant = variant[i];
+            h.ifs[i].flux_occ = occ[i];
+            h.ifs[i].tune_tile = tile[i];
+            h.ifs[i].tune_grid = grid[i];
+            h.ifs[i].cons_nb = 0;
+        }
+    }
+};
+
+static int autotune_timed(mortar_handle *h, const void *const *U_s, const void *const *U_m,
+                          const void *const *G_s, const void *const *G_m, void *const *F_s,
+                          void *const *F_m, int reps, hipStream_t st);
+
+static int autotune_run(mortar_handle *h, const void *const *U_s, const void *const *U_m,
+                        const void *const *G_s, const void *const *G_m, void *const *F_s,
+                        void *const *F_m, int reps, hipStream_t st)
+{
+    const TuningState saved(*h);
+    const int rc = autotune_timed(h, U_s, U_m, G_s, G_m, F_s, F_m, reps, st);
+    if (rc != MORTAR_OK) saved.restore(*h);
+    return rc;
+}
+
+static int autotune_timed(mortar_handle *h, const void *const *U_s, const void *const *U_m,
+                          const void *const *G_s, const void *const *G_m, void *const *F_s,
+                          void *const *F_m, int reps, hipStream_t st)
+{
+    const size_t n_if = h->ifs.size();
     h->tune_epoch++;
     const CacheFlush flush;
     float ms = 0.f;
@@ -1082,6 +1145,8 @@ int mortar_autotune(mortar_handle *h, const void *const *U_s, const void *const 
     }
     return MORTAR_OK;
 }
+
+extern "C" {
 
 int mortar_get_tuning(const mortar_handle *h, int iface, mortar_tuning *out)
 {

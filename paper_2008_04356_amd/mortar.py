@@ -238,6 +238,65 @@ def make_desc(spec, keep: Optional[list] = None) -> mortar_iface_desc:
 
 # ---- convenience object (torch tensors in, torch tensors out) ------------------------
 
+def _dtype_of(spec):
+    import torch
+    return torch.float64 if int(spec.precision) == FP64 else torch.float32
+
+
+def _check_tensor(t, spec, shape, what):
+    """A face array handed to the library: a contiguous CUDA tensor of the interface's
+    element type and the exact shape the kernels address (anything else would make them
+    read or write outside the allocation)."""
+    if t is None:
+        raise MortarError(f"invalid argument: {what}: missing tensor")
+    if not getattr(t, "is_cuda", False):
+        raise MortarError(f"invalid argument: {what}: must be a CUDA tensor")
+    if not t.is_contiguous():
+        raise MortarError(f"invalid argument: {what}: must be contiguous")
+    if t.dtype != _dtype_of(spec):
+        raise MortarError(f"invalid argument: {what}: dtype {t.dtype}, the interface needs {_dtype_of(spec)}")
+    if tuple(t.shape) != tuple(shape):
+        raise MortarError(f"invalid argument: {what}: shape {tuple(t.shape)}, the interface needs {tuple(shape)}")
+
+
+def _check_list(ts, specs, kind, what):
+    """kind: 'state' [5][P][n_face], 'grad' [3][5][P][n_face] (NS only; None for Euler),
+    'lift' [3][5][P][n_face]; side 's' or 'm' picks the static or moving column count."""
+    if ts is None:
+        if kind == "grad" and all(int(s.physics) != NAVIER_STOKES for s in specs):
+            return
+        raise MortarError(f"invalid argument: {what}: missing")
+    if len(ts) != len(specs):
+        raise MortarError(f"invalid argument: {what}: {len(ts)} entries for {len(specs)} interfaces")
+    side = what[-1]
+    for i, (t, sp) in enumerate(zip(ts, specs)):
+        nf = sp.n_face_static if side == "s" else sp.n_face_moving
+        P = (int(sp.N) + 1) ** 2
+        if kind == "grad":
+            if int(sp.physics) != NAVIER_STOKES:
+                continue
+            shape = (3, 5, P, nf)
+        elif kind == "lift":
+            shape = (3, 5, P, nf)
+        else:
+            shape = (5, P, nf)
+        _check_tensor(t, sp, shape, f"{what}[{i}]")
+
+
+def _check_disp(disp, specs, what):
+    if len(disp) != len(specs):
+        raise MortarError(f"invalid argument: {what}: {len(disp)} displacements for {len(specs)} interfaces")
+
+
+def _check_flux_args(specs, Us, Um, Gs, Gm, Fs, Fm):
+    _check_list(Us, specs, "state", "U_s")
+    _check_list(Um, specs, "state", "U_m")
+    _check_list(Gs, specs, "grad", "G_s")
+    _check_list(Gm, specs, "grad", "G_m")
+    _check_list(Fs, specs, "state", "F_s")
+    _check_list(Fm, specs, "state", "F_m")
+
+
 class MortarOperator:
     """Owns a library handle for a list of interfaces."""
 
@@ -267,14 +326,18 @@ class MortarOperator:
         return int(stream)
 
     def update(self, disp, stream=None):
+        _check_disp(disp, self.specs, "mortar_update_displacement")
         _check(mortar_update_displacement(self.h, disp, self._stream(stream)),
                "mortar_update_displacement")
 
     def update_ns(self, n, s, stream=None):
+        _check_disp(n, self.specs, "mortar_update_displacement_ns")
+        _check_disp(s, self.specs, "mortar_update_displacement_ns")
         _check(mortar_update_displacement_ns(self.h, n, s, self._stream(stream)),
                "mortar_update_displacement_ns")
 
     def flux(self, Us, Um, Gs, Gm, Fs, Fm, stream=None):
+        _check_flux_args(self.specs, Us, Um, Gs, Gm, Fs, Fm)
         p = lambda ts: None if ts is None else [None if t is None else t.data_ptr() for t in ts]  # noqa: E731
         _check(mortar_flux(self.h, p(Us), p(Um), p(Gs), p(Gm), p(Fs), p(Fm), self._stream(stream)),
                "mortar_flux")
@@ -287,6 +350,10 @@ class MortarOperator:
 
     def lifting(self, Us, Um, Ls, Lm, stream=None):
         """BR1 lifting surface term: Ls[i], Lm[i] [3][5][P][n_face] tensors (written)."""
+        _check_list(Us, self.specs, "state", "U_s")
+        _check_list(Um, self.specs, "state", "U_m")
+        _check_list(Ls, self.specs, "lift", "L_s")
+        _check_list(Lm, self.specs, "lift", "L_m")
         p = lambda ts: [t.data_ptr() for t in ts]  # noqa: E731
         _check(mortar_lifting(self.h, p(Us), p(Um), p(Ls), p(Lm), self._stream(stream)), "mortar_lifting")
 
@@ -322,6 +389,7 @@ class MortarOperator:
             if key in table:
                 self.set_tuning(table[key])
                 return table[key]
+        _check_flux_args(self.specs, Us, Um, Gs, Gm, Fs, Fm)
         p = lambda ts: None if ts is None else [None if t is None else t.data_ptr() for t in ts]  # noqa: E731
         _check(mortar_autotune(self.h, p(Us), p(Um), p(Gs), p(Gm), p(Fs), p(Fm), reps,
                                self._stream(stream)), "mortar_autotune")
@@ -369,13 +437,25 @@ class MortarOperator:
         """Captures one stage for these fixed buffers; see MortarGraph."""
         return MortarGraph(self, Us, Um, Gs, Gm, Fs, Fm)
 
+    def _check_cons(self, Fs, Fm, out=None):
+        import torch
+        _check_list(Fs, self.specs, "state", "F_s")
+        _check_list(Fm, self.specs, "state", "F_m")
+        if out is not None:
+            if not (getattr(out, "is_cuda", False) and out.is_contiguous() and out.dtype == torch.float64
+                    and tuple(out.shape) == (len(self.specs), 5, 3)):
+                raise MortarError(f"invalid argument: conservation output: needs a contiguous CUDA float64 tensor "
+                                  f"of shape ({len(self.specs)}, 5, 3)")
+
     def conservation_device(self, Fs, Fm, out, stream=None):
         """Asynchronous sums into the device tensor out (float64, [n_iface, 5, 3])."""
+        self._check_cons(Fs, Fm, out)
         p = lambda ts: _ptrs([t.data_ptr() for t in ts])  # noqa: E731
         _check(mortar_conservation_device(self.h, p(Fs), p(Fm), out.data_ptr(),
                                           self._stream(stream)), "mortar_conservation_device")
 
     def conservation(self, Fs, Fm, stream=None):
+        self._check_cons(Fs, Fm)
         out = np.zeros((len(self.specs), 5, 3))
         p = lambda ts: _ptrs([t.data_ptr() for t in ts])  # noqa: E731
         _check(lib.mortar_conservation(self.h, p(Fs), p(Fm), out.ctypes.data_as(_dp),
@@ -391,8 +471,12 @@ class MortarStage:
     the current stream at construction."""
 
     def __init__(self, op, Us, Um, Gs, Gm, Fs, Fm, cons_out=None, stream=None):
+        _check_flux_args(op.specs, Us, Um, Gs, Gm, Fs, Fm)
+        if cons_out is not None:
+            op._check_cons(Fs, Fm, cons_out)
         p = lambda ts: None if ts is None else _ptrs([None if t is None else t.data_ptr() for t in ts])  # noqa: E731
         self._keep = (op, Us, Um, Gs, Gm, Fs, Fm, cons_out)
+        self._n = len(op.specs)
         self._h = op.h
         self._args = (p(Us), p(Um), p(Gs), p(Gm), p(Fs), p(Fm))
         self._st = C.c_void_p(op._stream(stream))
@@ -401,6 +485,8 @@ class MortarStage:
             (self._args[4], self._args[5], C.c_void_p(cons_out.data_ptr()))
 
     def __call__(self, disp):
+        if len(disp) != self._n:
+            raise MortarError(f"invalid argument: mortar stage: {len(disp)} displacements for {self._n} interfaces")
         d = self._disp
         for i, x in enumerate(disp):
             d[i] = x
@@ -417,12 +503,14 @@ class MortarGraph:
     launch(disp) updates the displacement and replays the graph."""
 
     def __init__(self, op, Us, Um, Gs, Gm, Fs, Fm):
+        _check_flux_args(op.specs, Us, Um, Gs, Gm, Fs, Fm)
         p = lambda ts: None if ts is None else [None if t is None else t.data_ptr() for t in ts]  # noqa: E731
         self.op = op
         self._keep = (Us, Um, Gs, Gm, Fs, Fm)
         self.g = mortar_graph_create(op.h, p(Us), p(Um), p(Gs), p(Gm), p(Fs), p(Fm))
 
     def launch(self, disp, stream=None):
+        _check_disp(disp, self.op.specs, "mortar_graph_launch")
         _check(mortar_graph_launch(self.g, disp, MortarOperator._stream(stream)),
                "mortar_graph_launch")
 

@@ -12,7 +12,7 @@ from paper_2008_04356_amd import workloads as W
 
 from .test_gpu_batch import same
 from .test_gpu_lifting import _case as lifting_case
-from .test_gpu_lowprec import U_ROUND, _lowprec_case
+from .test_gpu_lowprec import _lowprec_case
 from .test_gpu_parity import _VARIANTS, _run_and_compare
 from . import _parity as H
 
@@ -91,8 +91,8 @@ def test_batch_of_curved_and_flat(M, precision):
 @pytest.mark.parametrize("precision", [W.BF16_MFMA, W.FP16_MFMA])
 def test_lowprec_cone(M, precision):
     spec = W.make_revolution(5, 24, 3, SHAPES["cone"], seed=7, precision=precision)
-    err = _lowprec_case(M, spec, [0.2 * spec.l_par, 3.7 * spec.l_par])
-    assert np.max(err) <= 64 * U_ROUND[precision]
+    # the derived per-variable bound is asserted inside the case
+    _lowprec_case(M, spec, [0.2 * spec.l_par, 3.7 * spec.l_par])
 
 
 @pytest.mark.parametrize("config,precision,variant",

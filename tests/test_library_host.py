@@ -111,3 +111,44 @@ def test_library_node_sets(M, node_set):
         M.mortar_basis(16, node_set)
     with pytest.raises(M.MortarError):
         M.mortar_basis(0, node_set)
+
+
+def test_binding_rejects_bad_face_arrays_before_the_library(M):
+    """The convenience layer checks every tensor against the interface before the C ABI
+    sees a pointer (the kernels address exactly [5][P][n_face] / [3][5][P][n_face] of
+    the interface's element type): CPU tensors, wrong dtype, wrong shape, views that are
+    not contiguous, missing gradients and wrong displacement counts are refused."""
+    import torch
+    ns = W.make_plane(2, 4, 2, physics=W.NS, riemann=W.ROE, mu=1e-3, precision=W.FP32)
+    eu = W.make_plane(2, 4, 2, physics=W.EULER, riemann=W.LF, precision=W.FP64)
+    P = ns.P
+    st = torch.zeros((5, P, ns.n_face_static), dtype=torch.float32)
+    gr = torch.zeros((3, 5, P, ns.n_face_static), dtype=torch.float32)
+    with pytest.raises(M.MortarError, match="CUDA"):
+        M._check_flux_args([ns], [st], [st], [gr], [gr], [st], [st])
+    with pytest.raises(M.MortarError, match="missing"):
+        M._check_list(None, [ns], "grad", "G_s")
+    with pytest.raises(M.MortarError, match="entries"):
+        M._check_list([st], [ns, ns], "state", "U_s")
+    # Euler interfaces take no gradients
+    M._check_list(None, [eu], "grad", "G_s")
+    M._check_list([None], [eu], "grad", "G_s")
+
+    class FakeCuda:
+        """Stands in for a device tensor (no GPU here): only the checked attributes."""
+        def __init__(self, shape, dtype, contiguous=True):
+            self.shape, self.dtype, self.is_cuda, self._c = shape, dtype, True, contiguous
+
+        def is_contiguous(self):
+            return self._c
+
+    ok = FakeCuda((5, P, ns.n_face_static), torch.float32)
+    M._check_tensor(ok, ns, (5, P, ns.n_face_static), "F_s[0]")
+    with pytest.raises(M.MortarError, match="dtype"):
+        M._check_tensor(FakeCuda((5, P, ns.n_face_static), torch.float64), ns, ok.shape, "F_s[0]")
+    with pytest.raises(M.MortarError, match="shape"):
+        M._check_tensor(FakeCuda((5, P, ns.n_face_static - 1), torch.float32), ns, ok.shape, "F_s[0]")
+    with pytest.raises(M.MortarError, match="contiguous"):
+        M._check_tensor(FakeCuda(ok.shape, torch.float32, contiguous=False), ns, ok.shape, "F_s[0]")
+    with pytest.raises(M.MortarError, match="displacements"):
+        M._check_disp([0.1, 0.2], [ns], "mortar_update_displacement")
