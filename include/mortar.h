@@ -263,6 +263,19 @@ int mortar_conservation(mortar_handle *h, const void *const *F_s, const void *co
 int mortar_conservation_device(mortar_handle *h, const void *const *F_s, const void *const *F_m,
                                double *d_out, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the sums of mortar_conservation_device
+ * (same arguments and output, always by a pass over the flux arrays) with their partial
+ * results in a static device array of the library instead of handle buffers.  Calls no
+ * allocating routine.  At most 8 interfaces per handle (UNSUPPORTED beyond; 1.25 MiB of
+ * partials, 160 KiB per interface, held on every device the library runs on until the
+ * process ends).  Every call on one device shares that array: calls that overlap on one
+ * device (different streams, or handles used from several threads) race; calls on one
+ * stream are ordered.  Every partial a call reads is written earlier in the same call, so
+ * nothing needs clearing between calls.  Asynchronous on stream. */
+int mortar_conservation_device_noalloc(mortar_handle *h, const void *const *F_s,
+                                       const void *const *F_m, double *d_out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

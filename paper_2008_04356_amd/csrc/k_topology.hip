@@ -5,6 +5,7 @@
 //    inverse map m, rebuilt when the displacement crosses a whole face;
 //  - FP64 compensated conservation sums of the face fluxes of both sides.
 #include <algorithm>
+#include <mutex>
 
 #include "assemble.h"
 #include "mortar_internal.h"
@@ -370,6 +371,42 @@ hipError_t launch_conservation(const Iface &f, const void *Fs, const void *Fm, d
                                hipStream_t st)
 {
     return launch_conservation_into(f, Fs, Fm, f.d_cons, d_out, st);
+}
+
+// ------------------------------------------------------------------------------------
+// Conservation sums without any allocation: the partials of every interface of a call
+// live in one file-scope device array (its own copy on every device the library runs
+// on, held until the process ends).  Host code never passes the array's name to a
+// kernel (in host code that name is not a device address): each device's address is
+// looked up once, with that device current, and kept in the handle.
+// ------------------------------------------------------------------------------------
+
+static __device__ __align__(256) double scratch[kStaticConsIfaces * kStaticConsSlot];
+
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t static_cons_scratch(int device, double **out)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = static_cast<double *>(ptr);
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+hipError_t launch_conservation_static(const Iface &f, int slot, double *scratch_ptr,
+                                      const void *Fs, const void *Fm, double *d_out, hipStream_t st)
+{
+    if (slot < 0 || slot >= kStaticConsIfaces || 20 * cons_face_blocks(f.F) > kStaticConsSlot)
+        return hipErrorInvalidValue;
+    return launch_conservation_into(f, Fs, Fm, scratch_ptr + (size_t)slot * kStaticConsSlot, d_out, st);
 }
 
 }  // namespace mortar

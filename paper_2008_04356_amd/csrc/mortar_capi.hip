@@ -567,6 +567,12 @@ int mortar_setup(const mortar_iface_desc *desc, int n_iface, mortar_handle **out
         delete h;
         return MORTAR_ERR_HIP;
     }
+    // the static partials array of mortar_conservation_device_noalloc: its address on
+    // this device, looked up once per device while the device is current
+    if (static_cons_scratch(h->device, &h->static_scratch) != hipSuccess) {
+        delete h;
+        return MORTAR_ERR_HIP;
+    }
     h->ifs.resize(n_iface);
     for (int i = 0; i < n_iface; ++i) {
         rc = setup_one(desc[i], h->ifs[i]);
@@ -755,6 +761,20 @@ int mortar_conservation_device(mortar_handle *h, const void *const *F_s, const v
         if (!F_s[i] || !F_m[i]) return MORTAR_ERR_INVALID_ARG;
     for (size_t i = 0; i < h->ifs.size(); ++i)
         TRY_HIP(launch_conservation_any(h->ifs[i], F_s[i], F_m[i], d_out + 15 * i, (hipStream_t)stream));
+    return MORTAR_OK;
+}
+
+int mortar_conservation_device_noalloc(mortar_handle *h, const void *const *F_s,
+                                       const void *const *F_m, double *d_out, void *stream)
+{
+    if (!h || !F_s || !F_m || !d_out) return MORTAR_ERR_INVALID_ARG;
+    if (h->ifs.size() > (size_t)kStaticConsIfaces) return MORTAR_ERR_UNSUPPORTED;
+    if (!h->static_scratch) return MORTAR_ERR_HIP;
+    for (size_t i = 0; i < h->ifs.size(); ++i)
+        if (!F_s[i] || !F_m[i]) return MORTAR_ERR_INVALID_ARG;
+    for (size_t i = 0; i < h->ifs.size(); ++i)
+        TRY_HIP(launch_conservation_static(h->ifs[i], (int)i, h->static_scratch, F_s[i], F_m[i],
+                                           d_out + 15 * i, (hipStream_t)stream));
     return MORTAR_OK;
 }
 

@@ -122,6 +122,7 @@ struct Handle {
     bool batch_rd_ok = false;          // the register-direct batch kernel covers the batch
     int batch_occ_rd = 1;
     unsigned tune_epoch = 0;           // bumped by every tuning change
+    double *static_scratch = nullptr;  // this device's address of the static partials array
     std::vector<Iface> ifs;
 };
 
@@ -142,6 +143,15 @@ constexpr int kConsGridMax = 4096;
 // offsets from there up to 4 GiB mark masked-off lanes.
 constexpr int64_t kRdMaxBytes = 0xFFFFFF00;
 hipError_t launch_conservation_final(const Iface &f, double *d_out, hipStream_t st);
+// Conservation sums with the partials in the library's static device array: at most
+// kStaticConsIfaces interfaces per call, one slot of kStaticConsSlot doubles each (10
+// groups x the conservation grid's at most 1024 blocks x 2).
+constexpr int kStaticConsIfaces = 8;
+constexpr int kStaticConsSlot = 10 * 1024 * 2;
+constexpr int kMaxDevices = 64;
+hipError_t static_cons_scratch(int device, double **out);
+hipError_t launch_conservation_static(const Iface &f, int slot, double *scratch_ptr,
+                                      const void *Fs, const void *Fm, double *d_out, hipStream_t st);
 hipError_t launch_conservation(const Iface &f, const void *Fs, const void *Fm, double *d_out,
                                hipStream_t st);
 

@@ -76,6 +76,7 @@ def _load():
     L.mortar_get_pairing.argtypes = [C.c_void_p, C.c_int, _ip]
     L.mortar_conservation.argtypes = [C.c_void_p, _vpp, _vpp, _dp, C.c_void_p]
     L.mortar_conservation_device.argtypes = [C.c_void_p, _vpp, _vpp, C.c_void_p, C.c_void_p]
+    L.mortar_conservation_device_noalloc.argtypes = [C.c_void_p, _vpp, _vpp, C.c_void_p, C.c_void_p]
     L.mortar_graph_create.argtypes = [C.c_void_p, _vpp, _vpp, _vpp, _vpp, _vpp, _vpp,
                                       C.POINTER(C.c_void_p)]
     L.mortar_graph_launch.argtypes = [C.c_void_p, _dp, C.c_void_p]
@@ -171,6 +172,10 @@ def mortar_set_tuning(h, iface: int, variant: int, tile_len: int = 0, grid: int 
 
 def mortar_conservation_device(h, Fs, Fm, d_out: int, stream: int = 0) -> int:
     return lib.mortar_conservation_device(h, Fs, Fm, C.c_void_p(int(d_out)), C.c_void_p(stream))
+
+
+def mortar_conservation_device_noalloc(h, Fs, Fm, d_out: int, stream: int = 0) -> int:
+    return lib.mortar_conservation_device_noalloc(h, Fs, Fm, C.c_void_p(int(d_out)), C.c_void_p(stream))
 
 
 def mortar_destroy(h) -> int:
@@ -453,6 +458,14 @@ class MortarOperator:
         p = lambda ts: _ptrs([t.data_ptr() for t in ts])  # noqa: E731
         _check(mortar_conservation_device(self.h, p(Fs), p(Fm), out.data_ptr(),
                                           self._stream(stream)), "mortar_conservation_device")
+
+    def conservation_device_noalloc(self, Fs, Fm, out, stream=None):
+        """The same sums with the library's static partials array (no allocation)."""
+        self._check_cons(Fs, Fm, out)
+        p = lambda ts: _ptrs([t.data_ptr() for t in ts])  # noqa: E731
+        _check(mortar_conservation_device_noalloc(self.h, p(Fs), p(Fm), out.data_ptr(),
+                                                  self._stream(stream)),
+               "mortar_conservation_device_noalloc")
 
     def conservation(self, Fs, Fm, stream=None):
         self._check_cons(Fs, Fm)
