@@ -46,11 +46,22 @@ def _compile(src):
     return obj, r.stderr
 
 
+# The DGSEM solver that embeds the operator in a whole scheme (its own library; it calls
+# nothing in libmortar.so, the driver passes device buffers between the two).
+DG_SOURCES = ["dg_embed.hip"]
+DG_OUT = os.path.join(HERE, "libdgembed.so")
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    jobs = min(len(SOURCES), int(os.environ.get("MAX_JOBS", "8")))
+    jobs = min(len(SOURCES) + len(DG_SOURCES), int(os.environ.get("MAX_JOBS", "8")))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        results = list(ex.map(_compile, SOURCES))
+        results = list(ex.map(_compile, SOURCES + DG_SOURCES))
+    dg_objs = [o for o, _ in results[len(SOURCES):]]
+    results = results[:len(SOURCES)]
+    tmp = DG_OUT + ".tmp"
+    subprocess.run(["hipcc", "-shared", f"--offload-arch={ARCH}", "-o", tmp, *dg_objs], check=True)
+    os.replace(tmp, DG_OUT)
     if verbose:
         for _, err in results:
             if err.strip():
