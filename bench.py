@@ -51,8 +51,9 @@ def parse():
     p.add_argument("--no-lifting", action="store_true",
                    help="skip the BR1 lifting leg (config.lifting)")
     p.add_argument("--tuning", default=None,
-                   help="VARIANT,TILE,GRID: launch the headline leg with this tuning on every "
-                        "interface instead of autotuning it")
+                   help="VARIANT,TILE,GRID: launch the headline leg with this tuning instead of "
+                        "autotuning it; TILE is one length for every interface or one per "
+                        "interface separated by '/'")
     p.add_argument("--copy-calibration", type=float, default=0.0,
                    help="only run a plain device copy of this many MB (counter calibration)")
     return p.parse_args()
@@ -188,7 +189,9 @@ def run_leg(M, W, specs, disp, steps, warmup, rotate_bytes, graph=False, plain=F
         tuning = []
         for i, op in enumerate(ops):
             op.update([disp(0)[i]] if plain else disp(0))
-            op.set_tuning([dict(zip(("variant", "tile_len", "grid"), fixed))] * len(op.specs))
+            v, tiles, g = fixed
+            tiles = tiles if len(tiles) == len(op.specs) else [tiles[0]] * len(op.specs)
+            op.set_tuning([{"variant": v, "tile_len": t, "grid": g} for t in tiles])
             tuning += op.tuning()
         print(f"[bench] fixed tuning: {tuning}", file=sys.stderr, flush=True)
     elif tune:
@@ -457,7 +460,10 @@ def main():
     prec = {"fp32": W.FP32, "bf16": W.BF16_MFMA, "fp16": W.FP16_MFMA}[a.precision]
     specs32, disp = W.config(a.config, precision=prec)
     graph = (a.graph or len(specs32) > 1) and not a.eager
-    fixed = None if a.tuning is None else tuple(int(x) for x in a.tuning.split(","))
+    fixed = None
+    if a.tuning is not None:
+        v, t, g = a.tuning.split(",")
+        fixed = (int(v), [int(x) for x in t.split("/")], int(g))
     r32 = run_leg(M, W, specs32, disp, a.steps, a.warmup, a.rotate_bytes, graph=graph,
                   tune=not a.no_autotune, tune_cache=a.tune_cache, fixed=fixed,
                   measure_lifting=not a.no_lifting)

@@ -16,7 +16,8 @@
 // fluxes in registers.  The back projection is a GEMM with K = the 2 NP mortar nodes of
 // a column, whose B operand is exactly those flux registers (one more DPP shift for the
 // moving side, whose upper mortar sits in the next column).  Nothing goes through LDS
-// after the prologue, and the waves of a workgroup never wait for each other.
+// after the prologue; the waves of a workgroup only meet at one barrier per round of
+// tiles, so that they fetch the cache lines their neighbouring tiles share together.
 //
 // Precision (PREC): 0 runs the GEMMs in the element type (v_mfma_{f32,f64}_16x16x4).
 // 1 / 2 round the GEMM operands to bf16 / fp16 (v_mfma_f32_16x16x16_{bf16,f16}, FP32
@@ -109,7 +110,7 @@ template <> struct RdOp<float, 2> {
     __device__ static __forceinline__ int row(int kq, int r) { return 4 * kq + r; }
 };
 
-template <int NP, bool NSV, bool MET, int KW>
+template <int NP, bool NSV, bool MET, int KW, int EB>
 struct RdCfg {
     static constexpr int V = NSV ? 20 : 5;                 // projected per side
     static constexpr int VS = V + (MET ? 4 : 0);           // static side adds the metrics
@@ -118,7 +119,7 @@ struct RdCfg {
     static constexpr int KSF = (NP + KW - 1) / KW;         // static forward K steps
     static constexpr int KSM = (2 * NP + KW - 1) / KW;     // moving forward K steps
     static constexpr int KSB = RB * 16 / KW;               // backward K steps
-    static constexpr int WAVES = 4;                        // independent waves per workgroup
+    static constexpr int WAVES = rd_waves(EB);             // waves per workgroup (lockstep)
     static constexpr int NT = 64 * WAVES;
 };
 
@@ -186,6 +187,9 @@ struct WaveCursor {
         k = base + (blockIdx.x / kXcds) * waves + wave;
     }
     __device__ bool valid() const { return k < limit; }
+    // some wave of this workgroup has a tile in the current round (the same answer for
+    // every wave of the workgroup)
+    __device__ bool round_valid(int wave) const { return k - wave < limit; }
     __device__ int tile() const { return k; }
     __device__ void next() { k += stride; }
 };
@@ -193,17 +197,23 @@ struct WaveCursor {
 // One interface: every workgroup assembles the stage's matrices, then its waves take
 // tiles from the interface's wave cursor.  work: LDS of 8 NP^2 doubles; mats: 8 NP^2
 // element-type values; wq: NP doubles.  Contains __syncthreads (all threads call it).
+// Navier-Stokes launches with 4-byte data also write the conservation partials of the
+// values they store: every lane adds w_p w_q F and its magnitude per (variable, side) into
+// its own LDS slots (acc, [20][NT] doubles), and at the end of the interface the
+// workgroup adds its lanes' slots in a fixed order (red: 320 doubles of scratch) into
+// a.cons (layout of FluxArgs).
 template <typename T, int NP, bool NSV, bool MET, int RIEM, int PREC>
-__device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work, T *mats, double *wq)
+__device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work, T *mats, double *wq,
+                                             double *acc, double *red)
 {
     using Op = RdOp<T, PREC>;
-    using C = RdCfg<NP, NSV, MET, Op::KW>;
+    using C = RdCfg<NP, NSV, MET, Op::KW, (int)sizeof(T)>;
     using op_t = typename Op::op_t;
     using acc_t = typename Op::acc_t;
     constexpr int V = C::V, VS = C::VS, NN = C::NN, RB = C::RB, E = Op::E, KW = Op::KW;
     constexpr int KSF = C::KSF, KSM = C::KSM, KSB = C::KSB, P = NN;
     constexpr int LF = KSF * E, LM = KSM * E;              // loaded values per lane and var
-    static_assert(C::NT == 256, "launch bounds");
+    static_assert(C::NT == 64 * rd_waves((int)sizeof(T)), "launch bounds");
     static_assert(NP <= 16, "one 16-row block of face nodes in the back projection");
 
     const int tid = threadIdx.x;
@@ -301,6 +311,13 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
     for (int r = 0; r < 4; ++r) {
         const int j = Op::row(kq, r);
         wj[r] = j < NP ? wq[j] : 0.0;
+    }
+    // conservation partials written with the fluxes: Navier-Stokes in the 4-byte modes
+    // (the FP64 kernel's registers are already spent: its partials come from a pass)
+    constexpr bool FUSE = NSV && sizeof(T) == 4;
+    if constexpr (FUSE) {
+#pragma unroll
+        for (int k = 0; k < 20; ++k) acc[k * C::NT + tid] = 0.0;
     }
 
     const int np_ = a.n_par;
@@ -452,18 +469,25 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
     // current one, before its loads: vector-memory operations complete in issue order,
     // so the current tile's loads (waited for anyway) retire the lookup, while a lookup
     // issued after the previous tile's stores would also wait for them.
+    // The waves of the workgroup go through the rounds of tiles together: every wave runs
+    // every round (a wave without a tile in the last round computes tile 0 and stores
+    // nothing), and a barrier starts each round.
     WaveCursor cur(a.n_tiles, C::WAVES, wave);
-    bool more = cur.valid();
-    TileGeom g = tile_geom(a, more ? cur.tile() : 0, NP);
+    bool more = cur.round_valid(wave);
+    bool mine = cur.valid();
+    TileGeom g = tile_geom(a, mine ? cur.tile() : 0, NP);
     int cs_c = col_s(g), cm_c = col_m(g);
     // the first columns are waited for here, so that the loop is entered, like every later
     // iteration, with no lookup outstanding
     asm volatile("" ::"v"(cs_c), "v"(cm_c));
     while (more) {
         const TileGeom gc = g;
+        const bool live_tile = mine;
         cur.next();
-        more = cur.valid();
-        g = tile_geom(a, more ? cur.tile() : 0, NP);   // tile 0: a dead lookup
+        more = cur.round_valid(wave);
+        mine = cur.valid();
+        g = tile_geom(a, mine ? cur.tile() : 0, NP);   // tile 0: a dead lookup
+        __builtin_amdgcn_s_barrier();
         const int cs_n = col_s(g), cm_n = col_m(g);
         // this tile's columns: the static face of slot col and the moving face of slot
         // col are also the faces this lane writes
@@ -586,8 +610,9 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
             }
 
         // ---- back projection onto both sides ----------------------------------------
-        const bool out_s = col >= 1 && col <= gc.nf;       // static face i0-1+col
-        const bool out_m = col < gc.nf;                    // moving face of slot col
+        const bool out_s = live_tile && col >= 1 && col <= gc.nf;   // static face i0-1+col
+        const bool out_m = live_tile && col < gc.nf;                // moving face of slot col
+        const double wpp = FUSE ? wq[gc.pp] : 0.0;                 // weight of the line
         const uint32_t line = (uint32_t)(NP * gc.pp);
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
@@ -669,6 +694,24 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
                     dm[r] += corr_m;
                 }
             }
+            if constexpr (FUSE) {
+                // the stored values (rounded to the element type), weighted w_p w_q
+                double ts = 0.0, tm = 0.0, ms = 0.0, mm = 0.0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const double ys = out_s ? wj[r] * (double)T(ds[r]) : 0.0;
+                    const double ym = out_m ? wj[r] * (double)T(dm[r]) : 0.0;
+                    ts += ys;
+                    ms += fabs(ys);
+                    tm += ym;
+                    mm += fabs(ym);
+                }
+                double *q = acc + tid;
+                q[(4 * v + 0) * C::NT] += wpp * ts;
+                q[(4 * v + 1) * C::NT] += wpp * ms;
+                q[(4 * v + 2) * C::NT] += wpp * tm;
+                q[(4 * v + 3) * C::NT] += wpp * mm;
+            }
             // every lane stores (no branch: a branch around a store leaves the compiler
             // unsure how many memory operations are outstanding, and it then waits for all
             // of them before the next); masked lanes get an offset beyond the array
@@ -685,15 +728,39 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
             }
         }
     }
+    if constexpr (FUSE) {
+        // the workgroup's partials: 16 chunks of NT / 16 lanes per slot, then the chunks,
+        // in fixed orders; partial g = 2 v + side at a.cons[(g * gridDim.x + block) * 2 + m]
+        constexpr int CH = C::NT / 16;
+        __syncthreads();
+        for (int t = tid; t < 320; t += C::NT) {
+            const int k = t >> 4, c = t & 15;
+            const double *q = acc + k * C::NT + c * CH;
+            double x = 0.0;
+            for (int l = 0; l < CH; ++l) x += q[l];
+            red[t] = x;
+        }
+        __syncthreads();
+        if (tid < 20 && a.cons) {
+            double x = 0.0;
+            for (int c = 0; c < 16; ++c) x += red[tid * 16 + c];
+            a.cons[((size_t)(tid >> 1) * gridDim.x + blockIdx.x) * 2 + (tid & 1)] = x;
+        }
+        __syncthreads();
+    }
 }
 
 template <typename T, int NP, bool NSV, bool MET, int RIEM, int PREC>
-__global__ __launch_bounds__(256) void k_mortar_flux_rd(FluxArgs<T> a)
+__global__ __launch_bounds__(64 * rd_waves((int)sizeof(T))) void k_mortar_flux_rd(FluxArgs<T> a)
 {
+    constexpr int NT = 64 * rd_waves((int)sizeof(T));
     __shared__ double work[assemble_scratch<NP>()];
     __shared__ T mats[8 * NP * NP];          // Pf[4][NP][NP], Pb[4][NP][NP]
     __shared__ double wq[NP];
-    rd_interface<T, NP, NSV, MET, RIEM, PREC>(a, work, mats, wq);
+    constexpr bool FUSE = NSV && sizeof(T) == 4;
+    __shared__ double acc[FUSE ? 20 * NT : 1];
+    __shared__ double red[FUSE ? 320 : 1];
+    rd_interface<T, NP, NSV, MET, RIEM, PREC>(a, work, mats, wq, acc, red);
 }
 
 // Every interface of a batch in one persistent launch (degrees N = 3, 5, 7, element type
@@ -701,18 +768,21 @@ __global__ __launch_bounds__(256) void k_mortar_flux_rd(FluxArgs<T> a)
 // XCD-aware wave cursor.  The bodies are inlined; the host launches this kernel only
 // for batches whose degrees are all in {3, 5, 7}.
 template <bool NSV, int RIEM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_mortar_flux_rd_batch(BatchArgs<float> b)
+__global__ __launch_bounds__(64 * rd_waves(4)) __attribute__((amdgpu_waves_per_eu(2))) void k_mortar_flux_rd_batch(BatchArgs<float> b)
 {
     constexpr int NPM = 8;
+    constexpr int NT = 64 * rd_waves(4);
     __shared__ double work[assemble_scratch<NPM>()];
     __shared__ float mats[8 * NPM * NPM];
     __shared__ double wq[NPM];
+    __shared__ double acc[NSV ? 20 * NT : 1];
+    __shared__ double red[NSV ? 320 : 1];
     for (int i = 0; i < b.n_if; ++i) {
         const bool met = b.met[i] != 0;
 #define MORTAR_RD_BATCH_NP(NPV)                                                               \
     if (b.np[i] == NPV) {                                                                     \
-        if (met) rd_interface<float, NPV, NSV, true, RIEM, 0>(b.a[i], work, mats, wq);        \
-        else rd_interface<float, NPV, NSV, false, RIEM, 0>(b.a[i], work, mats, wq);           \
+        if (met) rd_interface<float, NPV, NSV, true, RIEM, 0>(b.a[i], work, mats, wq, acc, red); \
+        else rd_interface<float, NPV, NSV, false, RIEM, 0>(b.a[i], work, mats, wq, acc, red);    \
         continue;                                                                             \
     }
         MORTAR_RD_BATCH_NP(4) MORTAR_RD_BATCH_NP(6) MORTAR_RD_BATCH_NP(8)
@@ -728,7 +798,7 @@ namespace mortar {
 template <typename T, int NP, bool NSV, bool MET, int RIEM, int PREC>
 static hipError_t rd_go(const FluxArgs<T> &a, int grid, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_mortar_flux_rd<T, NP, NSV, MET, RIEM, PREC>), dim3(grid), dim3(256), 0,
+    hipLaunchKernelGGL((k_mortar_flux_rd<T, NP, NSV, MET, RIEM, PREC>), dim3(grid), dim3(64 * rd_waves((int)sizeof(T))), 0,
                        st, a);
     return hipGetLastError();
 }
@@ -738,7 +808,7 @@ static int rd_occ1()
 {
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &nb, reinterpret_cast<const void *>(&k_mortar_flux_rd<T, NP, NSV, MET, RIEM, PREC>), 256,
+            &nb, reinterpret_cast<const void *>(&k_mortar_flux_rd<T, NP, NSV, MET, RIEM, PREC>), 64 * rd_waves((int)sizeof(T)),
             0) != hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;

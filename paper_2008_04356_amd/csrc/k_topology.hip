@@ -293,8 +293,8 @@ __global__ __launch_bounds__(256) void k_cons_partial(const T *__restrict__ Fs,
 // lane takes partials lane, lane + 64, ... with compensation, eight loads in flight
 // before any is added, then the xor tree); out[v][0] = static integral, out[v][1] =
 // moving integral, out[v][2] = sum of |terms|.
-__global__ __launch_bounds__(640) void k_cons_final(const double *__restrict__ part, int nb,
-                                                    double *__restrict__ out)
+__device__ __forceinline__ void cons_final_block(const double *__restrict__ part, int nb,
+                                                 double *__restrict__ out)
 {
     __shared__ double res[10][2];
     const int g = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -330,6 +330,25 @@ __global__ __launch_bounds__(640) void k_cons_final(const double *__restrict__ p
     }
 }
 
+__global__ __launch_bounds__(640) void k_cons_final(const double *__restrict__ part, int nb,
+                                                    double *__restrict__ out)
+{
+    cons_final_block(part, nb, out);
+}
+
+// The final pass of several interfaces in one launch, one workgroup each (the same
+// arithmetic, so the same bits, as one k_cons_final per interface).
+struct ConsFinalBatch {
+    const double *part[kMaxConsBatch];
+    double *out[kMaxConsBatch];
+    int nb[kMaxConsBatch];
+};
+
+__global__ __launch_bounds__(640) void k_cons_final_batch(ConsFinalBatch b)
+{
+    cons_final_block(b.part[blockIdx.x], b.nb[blockIdx.x], b.out[blockIdx.x]);
+}
+
 // Conservation grid: blocks along the faces (one face per thread, every point of it;
 // at most 1024 blocks, larger interfaces loop) for each of the 10 (variable, side) groups.
 static int cons_face_blocks(int nfaces) { return std::max(1, std::min(1024, (nfaces + 255) / 256)); }
@@ -339,6 +358,21 @@ int cons_blocks(int P, int nfaces)
 {
     (void)P;
     return cons_face_blocks(nfaces);
+}
+
+// Sums of several interfaces from the partials their fused flux launches wrote, one launch.
+hipError_t launch_conservation_final_batch(const Iface *const *fs, double *const *outs, int n,
+                                           hipStream_t st)
+{
+    if (n < 1 || n > kMaxConsBatch) return hipErrorInvalidValue;
+    ConsFinalBatch b{};
+    for (int i = 0; i < n; ++i) {
+        b.part[i] = fs[i]->d_cons_wg;
+        b.nb[i] = fs[i]->cons_nb;
+        b.out[i] = outs[i];
+    }
+    hipLaunchKernelGGL(k_cons_final_batch, dim3(n), dim3(640), 0, st, b);
+    return hipGetLastError();
 }
 
 // Sums from the partials a fused flux launch wrote (one per workgroup and group).

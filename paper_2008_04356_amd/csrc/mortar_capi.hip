@@ -486,6 +486,8 @@ template <typename T>
 void fill_args(const Iface &f, const void *Us, const void *Um, const void *Gs, const void *Gm,
                void *Fs, void *Fm, FluxArgs<T> &a, int &n_tiles);
 static int tiled_grid(const Iface &f, int n_cu, int nt);
+static int rd_grid_of(const Iface &f, int n_cu, int nt);
+static int rd_batch_grid(const Handle &h, int total);
 template <typename T>
 static void set_cons(const Iface &f, FluxArgs<T> &a, int grid, const void *Fs, const void *Fm);
 }  // namespace mortar
@@ -759,7 +761,25 @@ int mortar_conservation_device(mortar_handle *h, const void *const *F_s, const v
     if (!h || !F_s || !F_m || !d_out) return MORTAR_ERR_INVALID_ARG;
     for (size_t i = 0; i < h->ifs.size(); ++i)
         if (!F_s[i] || !F_m[i]) return MORTAR_ERR_INVALID_ARG;
-    for (size_t i = 0; i < h->ifs.size(); ++i)
+    // every interface's partials written by its last flux launch into these outputs: one
+    // final launch for all of them
+    const size_t n_if = h->ifs.size();
+    bool all_fused = n_if > 1 && n_if <= (size_t)kMaxConsBatch;
+    for (size_t i = 0; i < n_if && all_fused; ++i) {
+        const Iface &f = h->ifs[i];
+        all_fused = f.cons_nb > 0 && f.cons_Fs == F_s[i] && f.cons_Fm == F_m[i];
+    }
+    if (all_fused) {
+        const Iface *fs[kMaxConsBatch];
+        double *outs[kMaxConsBatch];
+        for (size_t i = 0; i < n_if; ++i) {
+            fs[i] = &h->ifs[i];
+            outs[i] = d_out + 15 * i;
+        }
+        TRY_HIP(launch_conservation_final_batch(fs, outs, (int)n_if, (hipStream_t)stream));
+        return MORTAR_OK;
+    }
+    for (size_t i = 0; i < n_if; ++i)
         TRY_HIP(launch_conservation_any(h->ifs[i], F_s[i], F_m[i], d_out + 15 * i, (hipStream_t)stream));
     return MORTAR_OK;
 }
@@ -883,6 +903,7 @@ int mortar_graph_launch(mortar_graph *g, const double *disp, void *stream)
         const bool f64 = h->ifs[0].elem == 8;
         auto build = [&](auto &b) {
             b.n_if = (int)n_if;
+            int total = 0;
             for (size_t i = 0; i < n_if; ++i) {
                 int nt = 0;
                 fill_args(h->ifs[i], g->Us[i], g->Um[i], g->Gs[i], g->Gm[i], g->Fs[i], g->Fm[i],
@@ -890,6 +911,13 @@ int mortar_graph_launch(mortar_graph *g, const double *disp, void *stream)
                 h->ifs[i].cons_nb = 0;
                 b.np[i] = h->ifs[i].NP;
                 b.met[i] = h->ifs[i].d_metrics != nullptr;
+                total += nt;
+            }
+            // the register-direct batch kernel writes each interface's partials (the grid
+            // is the one the captured launch was given)
+            if (h->batch_variant == 2) {
+                const int grid = rd_batch_grid(*h, total);
+                for (size_t i = 0; i < n_if; ++i) set_cons(h->ifs[i], b.a[i], grid, g->Fs[i], g->Fm[i]);
             }
         };
         if (f64) {
@@ -908,15 +936,17 @@ int mortar_graph_launch(mortar_graph *g, const double *disp, void *stream)
                 FluxArgs<double> a;
                 fill_args(h->ifs[i], g->Us[i], g->Um[i], g->Gs[i], g->Gm[i], g->Fs[i], g->Fm[i], a, nt);
                 h->ifs[i].cons_nb = 0;
-                if (h->ifs[i].flux_variant != 2)
-                    set_cons(h->ifs[i], a, tiled_grid(h->ifs[i], h->n_cu, nt), g->Fs[i], g->Fm[i]);
+                const int grid = h->ifs[i].flux_variant == 2 ? rd_grid_of(h->ifs[i], h->n_cu, nt)
+                                                             : tiled_grid(h->ifs[i], h->n_cu, nt);
+                set_cons(h->ifs[i], a, grid, g->Fs[i], g->Fm[i]);
                 rc = set_node_args(g, i, a);
             } else {
                 FluxArgs<float> a;
                 fill_args(h->ifs[i], g->Us[i], g->Um[i], g->Gs[i], g->Gm[i], g->Fs[i], g->Fm[i], a, nt);
                 h->ifs[i].cons_nb = 0;
-                if (h->ifs[i].flux_variant != 2)
-                    set_cons(h->ifs[i], a, tiled_grid(h->ifs[i], h->n_cu, nt), g->Fs[i], g->Fm[i]);
+                const int grid = h->ifs[i].flux_variant == 2 ? rd_grid_of(h->ifs[i], h->n_cu, nt)
+                                                             : tiled_grid(h->ifs[i], h->n_cu, nt);
+                set_cons(h->ifs[i], a, grid, g->Fs[i], g->Fm[i]);
                 rc = set_node_args(g, i, a);
             }
         }
@@ -1081,7 +1111,14 @@ static int autotune_timed(mortar_handle *h, const void *const *U_s, const void *
         if (log) std::fprintf(stderr, "[autotune] iface %d variant %d tile %d grid %d: %.2f us\n", iface, v, t, g, 1e3 * ms);
     };
     if (h->batched) {
-        auto run = [&]() { return launch_flux_batched(*h, U_s, U_m, G_s, G_m, F_s, F_m, st); };
+        // a candidate's time includes the stage's conservation sums (the partials some
+        // batch kernels write with the fluxes, else a pass over the arrays)
+        auto run = [&]() {
+            hipError_t e = launch_flux_batched(*h, U_s, U_m, G_s, G_m, F_s, F_m, st);
+            for (size_t i = 0; i < n_if && e == hipSuccess; ++i)
+                e = launch_conservation_any(h->ifs[i], F_s[i], F_m[i], h->ifs[i].d_cons_out, st);
+            return e;
+        };
         auto set_variant = [&](int v) {
             h->batch_variant = v;
             for (Iface &f : h->ifs) {
@@ -1257,6 +1294,15 @@ void fill_args(const Iface &f, const void *Us, const void *Um, const void *Gs,
     a.cons = nullptr;
 }
 
+// Grid of the register-direct kernel: one tile per wave, rd_waves() waves per workgroup,
+// at most the resident workgroups, at least one workgroup per XCD.
+static int rd_grid_of(const Iface &f, int n_cu, int nt)
+{
+    if (f.tune_grid > 0) return std::max(8, f.tune_grid);
+    const int w = rd_waves((int)f.elem);
+    return std::max(8, std::min((nt + w - 1) / w, f.flux_occ * n_cu));
+}
+
 // Persistent grid of the LDS-tiled kernels: at least min(8, n_tiles) workgroups so that
 // every XCD's share of the tiles has workers (TileCursor).
 static int tiled_grid(const Iface &f, int n_cu, int nt)
@@ -1265,12 +1311,19 @@ static int tiled_grid(const Iface &f, int n_cu, int nt)
     return std::max(1, std::min(nt, f.flux_occ * n_cu));
 }
 
-// The VALU-projection kernels (variants 0 and 3) also write the conservation partials of
-// their launch; record which outputs they belong to.
+// Kernels that also write the conservation partials of their launch: the VALU-projection
+// kernels (variants 0 and 3), and the register-direct kernels for Navier-Stokes with 4-byte
+// data; record which outputs the partials belong to.
+static bool writes_partials(const Iface &f, int variant)
+{
+    return variant == 0 || variant == 3 ||
+           (variant == 2 && f.d.physics == MORTAR_NAVIER_STOKES && f.elem == 4);
+}
+
 template <typename T>
 static void set_cons(const Iface &f, FluxArgs<T> &a, int grid, const void *Fs, const void *Fm)
 {
-    const bool fused = (f.flux_variant == 0 || f.flux_variant == 3) && grid <= kConsGridMax;
+    const bool fused = writes_partials(f, f.flux_variant) && grid <= kConsGridMax;
     a.cons = fused ? f.d_cons_wg : nullptr;
     f.cons_Fs = fused ? Fs : nullptr;
     f.cons_Fm = fused ? Fm : nullptr;
@@ -1286,19 +1339,19 @@ hipError_t launch_flux(const Iface &f, int n_cu, const void *Us, const void *Um,
     int n_tiles = 0;
     f.cons_nb = 0;
     if (f.flux_variant == 2) {
-        // one tile per wave, four waves per workgroup; at least one workgroup per XCD
-        auto rd_grid = [&](int nt) {
-            if (f.tune_grid > 0) return std::max(8, f.tune_grid);
-            return std::max(8, std::min((nt + 3) / 4, f.flux_occ * n_cu));
-        };
+        // one tile per wave, rd_waves() waves per workgroup; at least one workgroup per XCD
+        auto rd_grid = [&](int nt) { return rd_grid_of(f, n_cu, nt); };
         if (f.elem == 8) {
             FluxArgs<double> a;
             fill_args(f, Us, Um, Gs, Gm, Fs, Fm, a, n_tiles);
-            return launch_flux_rd_f64(a, f.NP, rd_grid(n_tiles), ns, met, riem, st);
+            const int grid = rd_grid(n_tiles);
+            set_cons(f, a, grid, Fs, Fm);
+            return launch_flux_rd_f64(a, f.NP, grid, ns, met, riem, st);
         }
         FluxArgs<float> a;
         fill_args(f, Us, Um, Gs, Gm, Fs, Fm, a, n_tiles);
         const int grid = rd_grid(n_tiles);
+        set_cons(f, a, grid, Fs, Fm);
         if (f.lp == 1) return launch_flux_rd_bf16(a, f.NP, grid, ns, met, riem, st);
         if (f.lp == 2) return launch_flux_rd_fp16(a, f.NP, grid, ns, met, riem, st);
         return launch_flux_rd_f32(a, f.NP, grid, ns, met, riem, st);
@@ -1319,6 +1372,13 @@ hipError_t launch_flux(const Iface &f, int n_cu, const void *Us, const void *Um,
     if (f.flux_variant == 4) return launch_flux_hyb_f32(a, f.NP, grid, ns, met, riem, st);
     return f.flux_variant == 1 ? launch_flux_mfma_f32(a, f.NP, grid, ns, met, riem, st)
                                : launch_flux_f32(a, f.NP, grid, ns, met, riem, st);
+}
+
+// Grid of the register-direct batch kernel for total tiles.
+static int rd_batch_grid(const Handle &h, int total)
+{
+    if (h.tune_grid_batch > 0) return std::max(8, h.tune_grid_batch);
+    return std::max(8, std::min((total + rd_waves(4) - 1) / rd_waves(4), h.batch_occ_rd * h.n_cu));
 }
 
 hipError_t launch_flux_batched(const Handle &h, const void *const *Us, const void *const *Um,
@@ -1347,11 +1407,11 @@ hipError_t launch_flux_batched(const Handle &h, const void *const *Us, const voi
         return std::max(1, std::min(nt, h.batch_occ * h.n_cu));
     };
     if (h.batch_variant == 2) {
-        // one tile per wave, four waves per workgroup; at least one workgroup per XCD
+        // one tile per wave, rd_waves() waves per workgroup; at least one workgroup per XCD
         BatchArgs<float> b;
         build(b);
-        const int grid = h.tune_grid_batch > 0 ? std::max(8, h.tune_grid_batch)
-                                               : std::max(8, std::min((total + 3) / 4, h.batch_occ_rd * h.n_cu));
+        const int grid = rd_batch_grid(h, total);
+        for (int i = 0; i < b.n_if; ++i) set_cons(h.ifs[i], b.a[i], grid, Fs[i], Fm[i]);
         return launch_flux_rd_batch_f32(b, grid, ns, riem, st);
     }
     if (f0.elem == 8) {

@@ -139,10 +139,20 @@ hipError_t launch_flux_batched(const Handle &h, const void *const *Us, const voi
 int cons_blocks(int P, int nfaces);
 // Largest flux grid whose workgroups write conservation partials.
 constexpr int kConsGridMax = 4096;
+// Waves of a register-direct workgroup.  They take consecutive tiles of one line and start
+// each round of tiles together (a workgroup barrier per round), so the cache lines that
+// neighbouring tiles share (a tile's 16 face slots span 64 bytes of each 128-byte line of
+// a (variable, node) row, and consecutive tiles overlap by the halo face) are requested
+// by several waves of one CU at about the same time and fetched from HBM once.  Eight
+// waves (two per SIMD) for 4-byte data; four for FP64, whose registers need a SIMD per wave.
+__host__ __device__ constexpr int rd_waves(int elem_bytes) { return elem_bytes == 8 ? 4 : 8; }
 // Largest array (bytes) the register-direct kernels address with 32-bit buffer offsets;
 // offsets from there up to 4 GiB mark masked-off lanes.
 constexpr int64_t kRdMaxBytes = 0xFFFFFF00;
 hipError_t launch_conservation_final(const Iface &f, double *d_out, hipStream_t st);
+constexpr int kMaxConsBatch = 8;
+hipError_t launch_conservation_final_batch(const Iface *const *fs, double *const *outs, int n,
+                                           hipStream_t st);
 // Conservation sums with the partials in the library's static device array: at most
 // kStaticConsIfaces interfaces per call, one slot of kStaticConsSlot doubles each (10
 // groups x the conservation grid's at most 1024 blocks x 2).
