@@ -87,14 +87,13 @@ __device__ __forceinline__ T entropy_fixed(T lam, T lamL, T lamR)
     return (a < delta) ? T(0.5) * (lam * lam * drcp(delta) + delta) : a;
 }
 
-// Convective numerical flux, RIEM = 0: local Lax-Friedrichs, 1: Roe + Harten-Hyman.
+// Convective numerical flux of two sides whose primitive states are already formed,
+// RIEM = 0: local Lax-Friedrichs, 1: Roe + Harten-Hyman.
 template <typename T, int RIEM>
-__device__ __forceinline__ void convective_flux(const T *UL, const T *UR, T nx, T ny, T nz,
-                                                const GasConsts<T> &g, T *F)
+__device__ __forceinline__ void convective_flux_sides(const Side<T> &L, const Side<T> &R,
+                                                      const T *UL, const T *UR, T nx, T ny, T nz,
+                                                      const GasConsts<T> &g, T *F)
 {
-    Side<T> L, R;
-    side_state(UL, nx, ny, nz, g, L);
-    side_state(UR, nx, ny, nz, g, R);
     if (RIEM == 0) {
         const T lam = dmax(dabs(L.vn) + L.c, dabs(R.vn) + R.c);
 #pragma unroll
@@ -147,15 +146,25 @@ __device__ __forceinline__ void convective_flux(const T *UL, const T *UR, T nx, 
     for (int v = 0; v < 5; ++v) F[v] = T(0.5) * ((L.F[v] + R.F[v]) - D[v]);
 }
 
-// Viscous normal flux Fv(U, grad U) . n of one side; G[d*5 + v] = dU_v/dx_d.
-template <typename T>
-__device__ __forceinline__ void viscous_flux(const T *U, const T *G, T nx, T ny, T nz,
-                                             const GasConsts<T> &g, T *Fv)
+// Convective numerical flux, RIEM = 0: local Lax-Friedrichs, 1: Roe + Harten-Hyman.
+template <typename T, int RIEM>
+__device__ __forceinline__ void convective_flux(const T *UL, const T *UR, T nx, T ny, T nz,
+                                                const GasConsts<T> &g, T *F)
 {
-    const T ir = drcp(U[0]);
-    const T v0 = U[1] * ir, v1 = U[2] * ir, v2 = U[3] * ir;
+    Side<T> L, R;
+    side_state(UL, nx, ny, nz, g, L);
+    side_state(UR, nx, ny, nz, g, R);
+    convective_flux_sides<T, RIEM>(L, R, UL, UR, nx, ny, nz, g, F);
+}
+
+// Viscous normal flux Fv(U, grad U) . n of one side from its 1/rho, velocity and p/rho;
+// G[d*5 + v] = dU_v/dx_d.
+template <typename T>
+__device__ __forceinline__ void viscous_flux_prim(const T ir, const T v0, const T v1, const T v2,
+                                                  const T p_over_r, const T *G, T nx, T ny, T nz,
+                                                  const GasConsts<T> &g, T *Fv)
+{
     const T half_v2 = T(0.5) * (v0 * v0 + v1 * v1 + v2 * v2);
-    const T p_over_r = g.gm1 * (U[4] * ir - half_v2);
     T gv[3][3];   // gv[i][d] = d v_i / d x_d
     T kgT[3];     // k dT/dx_d divided by nothing more: includes the gas-constant cancellation
 #pragma unroll
@@ -183,6 +192,26 @@ __device__ __forceinline__ void viscous_flux(const T *U, const T *G, T nx, T ny,
     Fv[2] = tn[1];
     Fv[3] = tn[2];
     Fv[4] = v0 * tn[0] + v1 * tn[1] + v2 * tn[2] + kgT[0] * nx + kgT[1] * ny + kgT[2] * nz;
+}
+
+// Viscous normal flux Fv(U, grad U) . n of one side; G[d*5 + v] = dU_v/dx_d.
+template <typename T>
+__device__ __forceinline__ void viscous_flux(const T *U, const T *G, T nx, T ny, T nz,
+                                             const GasConsts<T> &g, T *Fv)
+{
+    const T ir = drcp(U[0]);
+    const T v0 = U[1] * ir, v1 = U[2] * ir, v2 = U[3] * ir;
+    const T half_v2 = T(0.5) * (v0 * v0 + v1 * v1 + v2 * v2);
+    viscous_flux_prim(ir, v0, v1, v2, g.gm1 * (U[4] * ir - half_v2), G, nx, ny, nz, g, Fv);
+}
+
+// The same from the primitive state convective_flux_sides used (the side's 1/rho,
+// velocity and pressure are not formed again).
+template <typename T>
+__device__ __forceinline__ void viscous_flux_side(const Side<T> &S, const T *G, T nx, T ny, T nz,
+                                                  const GasConsts<T> &g, T *Fv)
+{
+    viscous_flux_prim(S.ir, S.u[0], S.u[1], S.u[2], S.p * S.ir, G, nx, ny, nz, g, Fv);
 }
 
 }  // namespace mortar

@@ -315,15 +315,19 @@ __device__ __forceinline__ void flux_points(const FluxArgs<T> &a, int nf, const 
                 unit_normal(nx, ny, nz);
             }
             T F[5];
-            convective_flux<T, RIEM>(UL, UR, nx, ny, nz, a.gas, F);
+            Side<T> SL, SR;
+            side_state(UL, nx, ny, nz, a.gas, SL);
+            side_state(UR, nx, ny, nz, a.gas, SR);
+            convective_flux_sides<T, RIEM>(SL, SR, UL, UR, nx, ny, nz, a.gas, F);
             if (NSV) {
+                // the viscous fluxes reuse the sides' 1/rho, velocities and pressures
                 T G[15], FvL[5], FvR[5];
 #pragma unroll
                 for (int gg = 0; gg < 15; ++gg) G[gg] = ldsS[((5 + gg) * NP + q) * LD + ms + 1];
-                viscous_flux(UL, G, nx, ny, nz, a.gas, FvL);
+                viscous_flux_side(SL, G, nx, ny, nz, a.gas, FvL);
 #pragma unroll
                 for (int gg = 0; gg < 15; ++gg) G[gg] = ldsM[((5 + gg) * NP + q) * LD + ms];
-                viscous_flux(UR, G, nx, ny, nz, a.gas, FvR);
+                viscous_flux_side(SR, G, nx, ny, nz, a.gas, FvR);
 #pragma unroll
                 for (int v = 0; v < 5; ++v) F[v] -= T(0.5) * (FvL[v] + FvR[v]);
             }

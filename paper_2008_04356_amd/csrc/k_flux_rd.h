@@ -16,8 +16,9 @@
 // fluxes in registers.  The back projection is a GEMM with K = the 2 NP mortar nodes of
 // a column, whose B operand is exactly those flux registers (one more DPP shift for the
 // moving side, whose upper mortar sits in the next column).  Nothing goes through LDS
-// after the prologue; the waves of a workgroup only meet at one barrier per round of
-// tiles, so that they fetch the cache lines their neighbouring tiles share together.
+// after the prologue; in the Navier-Stokes launches with 4-byte data the waves of a
+// workgroup meet at one barrier per round of tiles, so that they fetch the cache lines
+// their neighbouring tiles share together.
 //
 // Precision (PREC): 0 runs the GEMMs in the element type (v_mfma_{f32,f64}_16x16x4).
 // 1 / 2 round the GEMM operands to bf16 / fp16 (v_mfma_f32_16x16x16_{bf16,f16}, FP32
@@ -110,7 +111,7 @@ template <> struct RdOp<float, 2> {
     __device__ static __forceinline__ int row(int kq, int r) { return 4 * kq + r; }
 };
 
-template <int NP, bool NSV, bool MET, int KW, int EB>
+template <int NP, bool NSV, bool MET, int KW, int WV>
 struct RdCfg {
     static constexpr int V = NSV ? 20 : 5;                 // projected per side
     static constexpr int VS = V + (MET ? 4 : 0);           // static side adds the metrics
@@ -119,7 +120,7 @@ struct RdCfg {
     static constexpr int KSF = (NP + KW - 1) / KW;         // static forward K steps
     static constexpr int KSM = (2 * NP + KW - 1) / KW;     // moving forward K steps
     static constexpr int KSB = RB * 16 / KW;               // backward K steps
-    static constexpr int WAVES = rd_waves(EB);             // waves per workgroup (lockstep)
+    static constexpr int WAVES = WV;                       // waves per workgroup
     static constexpr int NT = 64 * WAVES;
 };
 
@@ -202,18 +203,18 @@ struct WaveCursor {
 // its own LDS slots (acc, [20][NT] doubles), and at the end of the interface the
 // workgroup adds its lanes' slots in a fixed order (red: 320 doubles of scratch) into
 // a.cons (layout of FluxArgs).
-template <typename T, int NP, bool NSV, bool MET, int RIEM, int PREC>
+template <typename T, int NP, bool NSV, bool MET, int RIEM, int PREC, int WV>
 __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work, T *mats, double *wq,
                                              double *acc, double *red)
 {
     using Op = RdOp<T, PREC>;
-    using C = RdCfg<NP, NSV, MET, Op::KW, (int)sizeof(T)>;
+    using C = RdCfg<NP, NSV, MET, Op::KW, WV>;
     using op_t = typename Op::op_t;
     using acc_t = typename Op::acc_t;
     constexpr int V = C::V, VS = C::VS, NN = C::NN, RB = C::RB, E = Op::E, KW = Op::KW;
     constexpr int KSF = C::KSF, KSM = C::KSM, KSB = C::KSB, P = NN;
     constexpr int LF = KSF * E, LM = KSM * E;              // loaded values per lane and var
-    static_assert(C::NT == 64 * rd_waves((int)sizeof(T)), "launch bounds");
+    static_assert(C::NT == 64 * WV, "launch bounds");
     static_assert(NP <= 16, "one 16-row block of face nodes in the back projection");
 
     const int tid = threadIdx.x;
@@ -469,11 +470,16 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
     // current one, before its loads: vector-memory operations complete in issue order,
     // so the current tile's loads (waited for anyway) retire the lookup, while a lookup
     // issued after the previous tile's stores would also wait for them.
-    // The waves of the workgroup go through the rounds of tiles together: every wave runs
-    // every round (a wave without a tile in the last round computes tile 0 and stores
-    // nothing), and a barrier starts each round.
+    // Navier-Stokes in 4-byte data: the waves of the workgroup go through the rounds of
+    // tiles together: every wave runs every round (a wave without a tile in the last round
+    // computes tile 0 and stores nothing), and a barrier starts each round.  This fetches
+    // the lines neighbouring tiles share once (the gradients make these launches the ones
+    // whose lines in flight exceed the L2); the other launches run their waves freely
+    // (with one wave per SIMD in FP64, or the fp16 scaling's cross-lane reductions, the
+    // barrier cost more than the fetches it saves).
+    constexpr bool LOCKSTEP = rd_lockstep((int)sizeof(T), NSV);
     WaveCursor cur(a.n_tiles, C::WAVES, wave);
-    bool more = cur.round_valid(wave);
+    bool more = LOCKSTEP ? cur.round_valid(wave) : cur.valid();
     bool mine = cur.valid();
     TileGeom g = tile_geom(a, mine ? cur.tile() : 0, NP);
     int cs_c = col_s(g), cm_c = col_m(g);
@@ -484,10 +490,10 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
         const TileGeom gc = g;
         const bool live_tile = mine;
         cur.next();
-        more = cur.round_valid(wave);
+        more = LOCKSTEP ? cur.round_valid(wave) : cur.valid();
         mine = cur.valid();
         g = tile_geom(a, mine ? cur.tile() : 0, NP);   // tile 0: a dead lookup
-        __builtin_amdgcn_s_barrier();
+        if constexpr (LOCKSTEP) __builtin_amdgcn_s_barrier();
         const int cs_n = col_s(g), cm_n = col_m(g);
         // this tile's columns: the static face of slot col and the moving face of slot
         // col are also the faces this lane writes
@@ -751,16 +757,17 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
 }
 
 template <typename T, int NP, bool NSV, bool MET, int RIEM, int PREC>
-__global__ __launch_bounds__(64 * rd_waves((int)sizeof(T))) void k_mortar_flux_rd(FluxArgs<T> a)
+__global__ __launch_bounds__(64 * rd_waves((int)sizeof(T), NSV)) void k_mortar_flux_rd(FluxArgs<T> a)
 {
-    constexpr int NT = 64 * rd_waves((int)sizeof(T));
+    constexpr int WV = rd_waves((int)sizeof(T), NSV);
+    constexpr int NT = 64 * WV;
     __shared__ double work[assemble_scratch<NP>()];
     __shared__ T mats[8 * NP * NP];          // Pf[4][NP][NP], Pb[4][NP][NP]
     __shared__ double wq[NP];
     constexpr bool FUSE = NSV && sizeof(T) == 4;
     __shared__ double acc[FUSE ? 20 * NT : 1];
     __shared__ double red[FUSE ? 320 : 1];
-    rd_interface<T, NP, NSV, MET, RIEM, PREC>(a, work, mats, wq, acc, red);
+    rd_interface<T, NP, NSV, MET, RIEM, PREC, WV>(a, work, mats, wq, acc, red);
 }
 
 // Every interface of a batch in one persistent launch (degrees N = 3, 5, 7, element type
@@ -768,10 +775,10 @@ __global__ __launch_bounds__(64 * rd_waves((int)sizeof(T))) void k_mortar_flux_r
 // XCD-aware wave cursor.  The bodies are inlined; the host launches this kernel only
 // for batches whose degrees are all in {3, 5, 7}.
 template <bool NSV, int RIEM>
-__global__ __launch_bounds__(64 * rd_waves(4)) __attribute__((amdgpu_waves_per_eu(2))) void k_mortar_flux_rd_batch(BatchArgs<float> b)
+__global__ __launch_bounds__(64 * kRdBatchWaves) __attribute__((amdgpu_waves_per_eu(2))) void k_mortar_flux_rd_batch(BatchArgs<float> b)
 {
     constexpr int NPM = 8;
-    constexpr int NT = 64 * rd_waves(4);
+    constexpr int NT = 64 * kRdBatchWaves;
     __shared__ double work[assemble_scratch<NPM>()];
     __shared__ float mats[8 * NPM * NPM];
     __shared__ double wq[NPM];
@@ -781,8 +788,8 @@ __global__ __launch_bounds__(64 * rd_waves(4)) __attribute__((amdgpu_waves_per_e
         const bool met = b.met[i] != 0;
 #define MORTAR_RD_BATCH_NP(NPV)                                                               \
     if (b.np[i] == NPV) {                                                                     \
-        if (met) rd_interface<float, NPV, NSV, true, RIEM, 0>(b.a[i], work, mats, wq, acc, red); \
-        else rd_interface<float, NPV, NSV, false, RIEM, 0>(b.a[i], work, mats, wq, acc, red);    \
+        if (met) rd_interface<float, NPV, NSV, true, RIEM, 0, kRdBatchWaves>(b.a[i], work, mats, wq, acc, red); \
+        else rd_interface<float, NPV, NSV, false, RIEM, 0, kRdBatchWaves>(b.a[i], work, mats, wq, acc, red);    \
         continue;                                                                             \
     }
         MORTAR_RD_BATCH_NP(4) MORTAR_RD_BATCH_NP(6) MORTAR_RD_BATCH_NP(8)
@@ -798,7 +805,7 @@ namespace mortar {
 template <typename T, int NP, bool NSV, bool MET, int RIEM, int PREC>
 static hipError_t rd_go(const FluxArgs<T> &a, int grid, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_mortar_flux_rd<T, NP, NSV, MET, RIEM, PREC>), dim3(grid), dim3(64 * rd_waves((int)sizeof(T))), 0,
+    hipLaunchKernelGGL((k_mortar_flux_rd<T, NP, NSV, MET, RIEM, PREC>), dim3(grid), dim3(64 * rd_waves((int)sizeof(T), NSV)), 0,
                        st, a);
     return hipGetLastError();
 }
@@ -808,7 +815,7 @@ static int rd_occ1()
 {
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &nb, reinterpret_cast<const void *>(&k_mortar_flux_rd<T, NP, NSV, MET, RIEM, PREC>), 64 * rd_waves((int)sizeof(T)),
+            &nb, reinterpret_cast<const void *>(&k_mortar_flux_rd<T, NP, NSV, MET, RIEM, PREC>), 64 * rd_waves((int)sizeof(T), NSV),
             0) != hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;

@@ -8,7 +8,7 @@ static int rd_batch_occ1()
 {
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &nb, reinterpret_cast<const void *>(&k_mortar_flux_rd_batch<NSV, RIEM>), 64 * rd_waves(4), 0) != hipSuccess)
+            &nb, reinterpret_cast<const void *>(&k_mortar_flux_rd_batch<NSV, RIEM>), 64 * kRdBatchWaves, 0) != hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }
@@ -23,11 +23,11 @@ hipError_t launch_flux_rd_batch_f32(const BatchArgs<float> &b, int grid, bool ns
                                     hipStream_t st)
 {
     if (ns) {
-        if (riem) hipLaunchKernelGGL((k_mortar_flux_rd_batch<true, 1>), dim3(grid), dim3(64 * rd_waves(4)), 0, st, b);
-        else hipLaunchKernelGGL((k_mortar_flux_rd_batch<true, 0>), dim3(grid), dim3(64 * rd_waves(4)), 0, st, b);
+        if (riem) hipLaunchKernelGGL((k_mortar_flux_rd_batch<true, 1>), dim3(grid), dim3(64 * kRdBatchWaves), 0, st, b);
+        else hipLaunchKernelGGL((k_mortar_flux_rd_batch<true, 0>), dim3(grid), dim3(64 * kRdBatchWaves), 0, st, b);
     } else {
-        if (riem) hipLaunchKernelGGL((k_mortar_flux_rd_batch<false, 1>), dim3(grid), dim3(64 * rd_waves(4)), 0, st, b);
-        else hipLaunchKernelGGL((k_mortar_flux_rd_batch<false, 0>), dim3(grid), dim3(64 * rd_waves(4)), 0, st, b);
+        if (riem) hipLaunchKernelGGL((k_mortar_flux_rd_batch<false, 1>), dim3(grid), dim3(64 * kRdBatchWaves), 0, st, b);
+        else hipLaunchKernelGGL((k_mortar_flux_rd_batch<false, 0>), dim3(grid), dim3(64 * kRdBatchWaves), 0, st, b);
     }
     return hipGetLastError();
 }

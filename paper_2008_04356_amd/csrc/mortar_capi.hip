@@ -1299,7 +1299,7 @@ void fill_args(const Iface &f, const void *Us, const void *Um, const void *Gs,
 static int rd_grid_of(const Iface &f, int n_cu, int nt)
 {
     if (f.tune_grid > 0) return std::max(8, f.tune_grid);
-    const int w = rd_waves((int)f.elem);
+    const int w = rd_waves((int)f.elem, f.d.physics == MORTAR_NAVIER_STOKES);
     return std::max(8, std::min((nt + w - 1) / w, f.flux_occ * n_cu));
 }
 
@@ -1378,7 +1378,7 @@ hipError_t launch_flux(const Iface &f, int n_cu, const void *Us, const void *Um,
 static int rd_batch_grid(const Handle &h, int total)
 {
     if (h.tune_grid_batch > 0) return std::max(8, h.tune_grid_batch);
-    return std::max(8, std::min((total + rd_waves(4) - 1) / rd_waves(4), h.batch_occ_rd * h.n_cu));
+    return std::max(8, std::min((total + kRdBatchWaves - 1) / kRdBatchWaves, h.batch_occ_rd * h.n_cu));
 }
 
 hipError_t launch_flux_batched(const Handle &h, const void *const *Us, const void *const *Um,

@@ -139,13 +139,18 @@ hipError_t launch_flux_batched(const Handle &h, const void *const *Us, const voi
 int cons_blocks(int P, int nfaces);
 // Largest flux grid whose workgroups write conservation partials.
 constexpr int kConsGridMax = 4096;
-// Waves of a register-direct workgroup.  They take consecutive tiles of one line and start
-// each round of tiles together (a workgroup barrier per round), so the cache lines that
-// neighbouring tiles share (a tile's 16 face slots span 64 bytes of each 128-byte line of
-// a (variable, node) row, and consecutive tiles overlap by the halo face) are requested
-// by several waves of one CU at about the same time and fetched from HBM once.  Eight
-// waves (two per SIMD) for 4-byte data; four for FP64, whose registers need a SIMD per wave.
-__host__ __device__ constexpr int rd_waves(int elem_bytes) { return elem_bytes == 8 ? 4 : 8; }
+// Waves of a register-direct workgroup; they take consecutive tiles of one line.  In the
+// Navier-Stokes launches with 4-byte data they start each round of tiles together (a
+// workgroup barrier per round), so the cache lines that neighbouring tiles share (a tile's
+// 16 face slots span 64 bytes of each 128-byte line of a (variable, node) row, and
+// consecutive tiles overlap by the halo face) are requested by several waves of one CU at
+// about the same time and fetched from HBM once: eight waves (two per SIMD, the occupancy
+// of those launches).  The other launches run four independent waves per workgroup (the
+// finer granularity keeps their higher occupancy).
+__host__ __device__ constexpr bool rd_lockstep(int elem_bytes, bool ns) { return ns && elem_bytes == 4; }
+__host__ __device__ constexpr int rd_waves(int elem_bytes, bool ns) { return rd_lockstep(elem_bytes, ns) ? 8 : 4; }
+// the batch kernel (4-byte data, both physics): eight waves
+constexpr int kRdBatchWaves = 8;
 // Largest array (bytes) the register-direct kernels address with 32-bit buffer offsets;
 // offsets from there up to 4 GiB mark masked-off lanes.
 constexpr int64_t kRdMaxBytes = 0xFFFFFF00;
