@@ -15,10 +15,10 @@
 // values of the same mortar nodes for every variable and evaluates their Riemann + BR1
 // fluxes in registers.  The back projection is a GEMM with K = the 2 NP mortar nodes of
 // a column, whose B operand is exactly those flux registers (one more DPP shift for the
-// moving side, whose upper mortar sits in the next column).  Nothing goes through LDS
-// after the prologue; in the Navier-Stokes launches with 4-byte data the waves of a
-// workgroup meet at one barrier per round of tiles, so that they fetch the cache lines
-// their neighbouring tiles share together.
+// moving side, whose upper mortar sits in the next column).  After the prologue only the
+// conservation partials of the 4-byte launches go through LDS; in the Navier-Stokes
+// launches with 4-byte data the waves of a workgroup meet at one barrier per round of
+// tiles, so that they fetch the cache lines their neighbouring tiles share together.
 //
 // Precision (PREC): 0 runs the GEMMs in the element type (v_mfma_{f32,f64}_16x16x4).
 // 1 / 2 round the GEMM operands to bf16 / fp16 (v_mfma_f32_16x16x16_{bf16,f16}, FP32
@@ -198,8 +198,8 @@ struct WaveCursor {
 // One interface: every workgroup assembles the stage's matrices, then its waves take
 // tiles from the interface's wave cursor.  work: LDS of 8 NP^2 doubles; mats: 8 NP^2
 // element-type values; wq: NP doubles.  Contains __syncthreads (all threads call it).
-// Navier-Stokes launches with 4-byte data also write the conservation partials of the
-// values they store: every lane adds w_p w_q F and its magnitude per (variable, side) into
+// Launches with 4-byte data (FP32, bf16, fp16) also write the conservation partials of
+// the values they store: every lane adds w_p w_q F and its magnitude per (variable, side) into
 // its own LDS slots (acc, [20][NT] doubles), and at the end of the interface the
 // workgroup adds its lanes' slots in a fixed order (red: 320 doubles of scratch) into
 // a.cons (layout of FluxArgs).
@@ -219,7 +219,7 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int col = lane & 15;               // slot of this lane
     const int kq = lane >> 4;                // operand K group / result row group
 
@@ -313,9 +313,9 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
         const int j = Op::row(kq, r);
         wj[r] = j < NP ? wq[j] : 0.0;
     }
-    // conservation partials written with the fluxes: Navier-Stokes in the 4-byte modes
-    // (the FP64 kernel's registers are already spent: its partials come from a pass)
-    constexpr bool FUSE = NSV && sizeof(T) == 4;
+    // conservation partials written with the fluxes in the 4-byte modes (the FP64
+    // kernel's registers are already spent: its partials come from a pass)
+    constexpr bool FUSE = sizeof(T) == 4;
     if constexpr (FUSE) {
 #pragma unroll
         for (int k = 0; k < 20; ++k) acc[k * C::NT + tid] = 0.0;
@@ -472,11 +472,12 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
     // issued after the previous tile's stores would also wait for them.
     // Navier-Stokes in 4-byte data: the waves of the workgroup go through the rounds of
     // tiles together: every wave runs every round (a wave without a tile in the last round
-    // computes tile 0 and stores nothing), and a barrier starts each round.  This fetches
-    // the lines neighbouring tiles share once (the gradients make these launches the ones
-    // whose lines in flight exceed the L2); the other launches run their waves freely
-    // (with one wave per SIMD in FP64, or the fp16 scaling's cross-lane reductions, the
-    // barrier cost more than the fetches it saves).
+    // computes tile 0 and stores nothing), and one barrier per round and wave keeps them
+    // together, in two groups out of phase (kRdPingPong).  This fetches the lines
+    // neighbouring tiles share once (the gradients make these launches the ones whose
+    // lines in flight exceed the L2); the other launches run their waves freely (with one
+    // wave per SIMD in FP64, or the fp16 scaling's cross-lane reductions, the barrier cost
+    // more than the fetches it saves).
     constexpr bool LOCKSTEP = rd_lockstep((int)sizeof(T), NSV);
     WaveCursor cur(a.n_tiles, C::WAVES, wave);
     bool more = LOCKSTEP ? cur.round_valid(wave) : cur.valid();
@@ -493,7 +494,11 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
         more = LOCKSTEP ? cur.round_valid(wave) : cur.valid();
         mine = cur.valid();
         g = tile_geom(a, mine ? cur.tile() : 0, NP);   // tile 0: a dead lookup
-        if constexpr (LOCKSTEP) __builtin_amdgcn_s_barrier();
+        // every wave passes one barrier per round: here, or (first group of the
+        // ping-pong) once the round's loads are issued
+        if constexpr (LOCKSTEP) {
+            if (!kRdPingPong || wave >= WV / 2) __builtin_amdgcn_s_barrier();
+        }
         const int cs_n = col_s(g), cm_n = col_m(g);
         // this tile's columns: the static face of slot col and the moving face of slot
         // col are also the faces this lane writes
@@ -502,6 +507,9 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
         fetch_m(gc, oc_m);
         // every load of the tile is issued before the first is used
         __builtin_amdgcn_sched_barrier(0);
+        if constexpr (LOCKSTEP && kRdPingPong) {
+            if (wave < WV / 2) __builtin_amdgcn_s_barrier();
+        }
         cs_c = cs_n;
         cm_c = cm_n;
         acc_t QL[5][RB], QR[5][RB], MT[MET ? 4 : 1][RB];
@@ -764,7 +772,7 @@ __global__ __launch_bounds__(64 * rd_waves((int)sizeof(T), NSV)) void k_mortar_f
     __shared__ double work[assemble_scratch<NP>()];
     __shared__ T mats[8 * NP * NP];          // Pf[4][NP][NP], Pb[4][NP][NP]
     __shared__ double wq[NP];
-    constexpr bool FUSE = NSV && sizeof(T) == 4;
+    constexpr bool FUSE = sizeof(T) == 4;
     __shared__ double acc[FUSE ? 20 * NT : 1];
     __shared__ double red[FUSE ? 320 : 1];
     rd_interface<T, NP, NSV, MET, RIEM, PREC, WV>(a, work, mats, wq, acc, red);
@@ -782,8 +790,8 @@ __global__ __launch_bounds__(64 * kRdBatchWaves) __attribute__((amdgpu_waves_per
     __shared__ double work[assemble_scratch<NPM>()];
     __shared__ float mats[8 * NPM * NPM];
     __shared__ double wq[NPM];
-    __shared__ double acc[NSV ? 20 * NT : 1];
-    __shared__ double red[NSV ? 320 : 1];
+    __shared__ double acc[20 * NT];
+    __shared__ double red[320];
     for (int i = 0; i < b.n_if; ++i) {
         const bool met = b.met[i] != 0;
 #define MORTAR_RD_BATCH_NP(NPV)                                                               \

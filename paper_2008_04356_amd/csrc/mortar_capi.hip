@@ -1312,12 +1312,11 @@ static int tiled_grid(const Iface &f, int n_cu, int nt)
 }
 
 // Kernels that also write the conservation partials of their launch: the VALU-projection
-// kernels (variants 0 and 3), and the register-direct kernels for Navier-Stokes with 4-byte
-// data; record which outputs the partials belong to.
+// kernels (variants 0 and 3), and the register-direct kernels with 4-byte data (FP32,
+// bf16, fp16); record which outputs the partials belong to.
 static bool writes_partials(const Iface &f, int variant)
 {
-    return variant == 0 || variant == 3 ||
-           (variant == 2 && f.d.physics == MORTAR_NAVIER_STOKES && f.elem == 4);
+    return variant == 0 || variant == 3 || (variant == 2 && f.elem == 4);
 }
 
 template <typename T>

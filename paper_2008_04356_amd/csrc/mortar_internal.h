@@ -147,10 +147,19 @@ constexpr int kConsGridMax = 4096;
 // about the same time and fetched from HBM once: eight waves (two per SIMD, the occupancy
 // of those launches).  The other launches run four independent waves per workgroup (the
 // finer granularity keeps their higher occupancy).
+constexpr int kRdLockWaves = 8;
+// The lockstep waves go in two groups out of phase: waves WV/2.. meet at the top of a
+// round, waves 0..WV/2-1 after issuing the round's loads.  A barrier then releases the
+// first group into its wait for the loads it has just issued while the second group
+// issues its own, and the first group issues the next round's loads as soon as its
+// arithmetic is done, while the second group still computes: each group's load latency
+// overlaps the other group's arithmetic on the same CU, where one barrier for all would
+// have every wave of the CU wait for memory at once.
+constexpr bool kRdPingPong = true;
 __host__ __device__ constexpr bool rd_lockstep(int elem_bytes, bool ns) { return ns && elem_bytes == 4; }
-__host__ __device__ constexpr int rd_waves(int elem_bytes, bool ns) { return rd_lockstep(elem_bytes, ns) ? 8 : 4; }
-// the batch kernel (4-byte data, both physics): eight waves
-constexpr int kRdBatchWaves = 8;
+__host__ __device__ constexpr int rd_waves(int elem_bytes, bool ns) { return rd_lockstep(elem_bytes, ns) ? kRdLockWaves : 4; }
+// the batch kernel (4-byte data, both physics)
+constexpr int kRdBatchWaves = kRdLockWaves;
 // Largest array (bytes) the register-direct kernels address with 32-bit buffer offsets;
 // offsets from there up to 4 GiB mark masked-off lanes.
 constexpr int64_t kRdMaxBytes = 0xFFFFFF00;

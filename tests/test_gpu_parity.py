@@ -340,16 +340,21 @@ def test_turbine_batch_full_size_all_rows(M, variant):
         op.close()
 
 
-@pytest.mark.parametrize("precision,variant,tile,grid,n_par", [
-    (W.FP32, 0, 0, 0, 70), (W.FP32, 3, 0, 0, 70), (W.FP32, 0, 7, 8, 70),
-    (W.FP64, 0, 0, 0, 70), (W.FP32, 0, 0, 0, 3), (W.FP32, 2, 0, 0, 70), (W.FP32, 4, 0, 0, 70)])
-def test_fused_conservation_sums(M, precision, variant, tile, grid, n_par):
-    """The VALU kernels write per-workgroup conservation partials with their fluxes; the
-    sums taken from them (same output arrays) agree with a pass over copies of the
-    arrays to FP64 rounding, on the device and on the host alike, also with workgroups
-    that get no tile (3 faces per row) and with other variants (a pass in both cases)."""
+@pytest.mark.parametrize("precision,variant,tile,grid,n_par,physics", [
+    (W.FP32, 0, 0, 0, 70, W.NS), (W.FP32, 3, 0, 0, 70, W.NS), (W.FP32, 0, 7, 8, 70, W.NS),
+    (W.FP64, 0, 0, 0, 70, W.NS), (W.FP32, 0, 0, 0, 3, W.NS), (W.FP32, 2, 0, 0, 70, W.NS),
+    (W.FP32, 4, 0, 0, 70, W.NS), (W.FP64, 2, 0, 0, 70, W.NS), (W.FP32, 2, 0, 0, 70, W.EULER),
+    (W.FP32, 2, 0, 8, 3, W.EULER), (W.BF16_MFMA, 2, 0, 0, 70, W.EULER),
+    (W.FP16_MFMA, 2, 0, 0, 70, W.NS)])
+def test_fused_conservation_sums(M, precision, variant, tile, grid, n_par, physics):
+    """The VALU kernels and the register-direct kernels with 4-byte data write
+    per-workgroup conservation partials with their fluxes; the sums taken from them (same
+    output arrays) agree with a pass over copies of the arrays to FP64 rounding, on the
+    device and on the host alike, also with workgroups that get no tile (3 faces per row)
+    and with the kernels that write none (a pass in both cases)."""
     import torch
-    spec = W.make_plane(5, n_par, 3, physics=W.NS, riemann=W.ROE, mu=1e-3, precision=precision,
+    spec = W.make_plane(5, n_par, 3, physics=physics, riemann=W.ROE,
+                        mu=1e-3 if physics == W.NS else 0.0, precision=precision,
                         scramble_seed=4, extra_cols=2)
     op = M.MortarOperator([spec])
     try:
@@ -365,11 +370,12 @@ def test_fused_conservation_sums(M, precision, variant, tile, grid, n_par):
         assert np.array_equal(dev.cpu().numpy()[0], fused)
         copies = (outs[0][0].clone(), outs[0][1].clone())
         passed = op.conservation([copies[0]], [copies[1]])[0]
-        print(f"[parity] conservation variant {variant}: fused {fused[:, :2].ravel()[:4]} "
+        print(f"[parity] conservation variant {variant} precision {precision} physics {physics}: "
+              f"fused {fused[:, :2].ravel()[:4]} "
               f"pass {passed[:, :2].ravel()[:4]}", flush=True)
         assert np.all(np.abs(fused - passed) <= 1e-13 * passed[:, 2:3] + 1e-300), (fused, passed)
         # the static and moving integrals agree to the storage rounding of the fluxes
-        tol = 2e-6 if precision == W.FP32 else 1e-13
+        tol = 1e-13 if precision == W.FP64 else 2e-6
         assert np.all(np.abs(fused[:, 0] - fused[:, 1]) <= tol * fused[:, 2])
     finally:
         op.close()
