@@ -154,6 +154,58 @@ __device__ __forceinline__ double rd_right(double x)
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// Cross-row exchanges without LDS (gfx950 permlane swaps): for each row of 16 lanes,
+// rd_rows16 returns the pair (value of rows 2k, value of rows 2k+1) and rd_rows32 the pair
+// (value of lanes l mod 32, value of lanes 32 + l mod 32), the same in both lanes of a
+// pair; their sum equals x + shfl_xor(x, 16) (resp. 32) bit for bit (one commutative add).
+__device__ __forceinline__ void rd_rows16(uint32_t x, uint32_t &a, uint32_t &b)
+{
+    const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    a = r[0];
+    b = r[1];
+}
+__device__ __forceinline__ void rd_rows32(uint32_t x, uint32_t &a, uint32_t &b)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    a = r[0];
+    b = r[1];
+}
+// Sum of x over the four lanes col + 16 m (m = 0..3) of every column, in every lane.
+__device__ __forceinline__ double rd_column_sum(double x)
+{
+#pragma unroll
+    for (int step = 0; step < 2; ++step) {
+        const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+        uint32_t alo, blo, ahi, bhi;
+        if (step == 0) {
+            rd_rows16((uint32_t)u, alo, blo);
+            rd_rows16((uint32_t)(u >> 32), ahi, bhi);
+        } else {
+            rd_rows32((uint32_t)u, alo, blo);
+            rd_rows32((uint32_t)(u >> 32), ahi, bhi);
+        }
+        const double p = __longlong_as_double((long long)(((unsigned long long)ahi << 32) | alo));
+        const double q = __longlong_as_double((long long)(((unsigned long long)bhi << 32) | blo));
+        x = p + q;
+    }
+    return x;
+}
+// Largest value of m over the wave, in every lane (non-negative m).
+__device__ __forceinline__ float rd_wave_max(float m)
+{
+    uint32_t a, b;
+    rd_rows16(__float_as_uint(m), a, b);
+    m = fmaxf(__uint_as_float(a), __uint_as_float(b));
+    rd_rows32(__float_as_uint(m), a, b);
+    m = fmaxf(__uint_as_float(a), __uint_as_float(b));
+    // within each row of 16 lanes: rotations by 8, 4, 2, 1
+    m = fmaxf(m, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(m), 0x128, 0xF, 0xF, false)));
+    m = fmaxf(m, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(m), 0x124, 0xF, 0xF, false)));
+    m = fmaxf(m, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(m), 0x122, 0xF, 0xF, false)));
+    m = fmaxf(m, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(m), 0x121, 0xF, 0xF, false)));
+    return m;
+}
+
 // fp16 operands: a power-of-two scale per wave and operand set keeps the values in the
 // normal range of fp16 (surface elements of fine meshes push fluxes below 6e-5, where
 // fp16 loses precision and then flushes to zero).  Scaling by powers of two is exact, so
@@ -161,8 +213,7 @@ __device__ __forceinline__ double rd_right(double x)
 // up to m (the largest magnitude in this lane); maps the wave's largest into [1, 2).
 __device__ __forceinline__ float rd_fp16_scale(float m, float &inv)
 {
-#pragma unroll
-    for (int k = 1; k < 64; k <<= 1) m = fmaxf(m, __shfl_xor(m, k));
+    m = rd_wave_max(m);
     const int ex = (int)((__float_as_uint(m) >> 23) & 0xFF) - 127;
     if (!(m > 0.0f) || ex > 126 || ex < -126) {   // zero, non-finite or extreme: no scaling
         inv = 1.0f;
@@ -693,13 +744,10 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
                     Am += wj[r] * (double)dm[r];
                 }
                 // sum over the four row groups of the column (lanes col + 16 m)
-#pragma unroll
-                for (int m = 16; m <= 32; m *= 2) {
-                    Ts += __shfl_xor(Ts, m);
-                    Tm += __shfl_xor(Tm, m);
-                    As += __shfl_xor(As, m);
-                    Am += __shfl_xor(Am, m);
-                }
+                Ts = rd_column_sum(Ts);
+                Tm = rd_column_sum(Tm);
+                As = rd_column_sum(As);
+                Am = rd_column_sum(Am);
                 const float corr_s = (float)(0.5 * (Ts - As));   // the weights sum to 2
                 const float corr_m = (float)(0.5 * (Tm - Am));
 #pragma unroll
