@@ -381,6 +381,82 @@ def test_fused_conservation_sums(M, precision, variant, tile, grid, n_par, physi
         op.close()
 
 
+@pytest.mark.parametrize("precision", [W.FP32, W.BF16_MFMA])
+def test_register_direct_schedule_any_grid(M, precision):
+    """The register-direct Navier-Stokes launch with 4-byte data runs its waves in rounds
+    of consecutive tiles (two groups out of phase, one barrier per round and wave).  Its
+    fluxes do not depend on the grid, bit for bit: one workgroup per XCD (several rounds,
+    a last round with waves that have no tile), XCDs with different numbers of
+    workgroups, more waves than tiles, workgroups with no tile at all.  The conservation
+    sums from each launch's fused partials agree with a pass over the arrays to FP64
+    rounding, and the fluxes with the oracle."""
+    import torch
+    spec = W.make_annulus(7, 64, 5, seed=17, precision=precision, name="annulus N=7 64x5")
+    inp = W.make_inputs(spec, seed=8, noise=1e-3)
+    din, oin = H.device_inputs(spec, inp), H.oracle_inputs(spec, inp)
+    d = 2.37 * spec.l_par
+    op = M.MortarOperator([spec])
+    try:
+        op.update([d])
+        first = None
+        for grid in (8, 13, 40, 0, 520):
+            print(f"[parity] register-direct schedule grid {grid} precision {precision}", flush=True)
+            assert M.mortar_set_tuning(op.h, 0, M.KERNEL_REGISTER, 0, grid) == 0
+            out = H.gpu_flux(op, [spec], [din], outs=[H.alloc_outputs(spec, fill=0.0)])[0]
+            fused = op.conservation([out[0]], [out[1]])[0]
+            passed = op.conservation([out[0].clone()], [out[1].clone()])[0]
+            assert np.all(np.abs(fused - passed) <= 1e-13 * passed[:, 2:3] + 1e-300), (grid, fused, passed)
+            if first is None:
+                first = out
+                n, sf = O.decompose(d, spec.l_par)
+                ref = H.oracle_flux(spec, oin, n, sf)
+                err = H.rel_err(spec, (out[0].cpu().numpy(), out[1].cpu().numpy()), ref)
+                if precision == W.FP32:
+                    assert np.max(err) <= H.TOL[W.FP32], err
+                else:
+                    assert np.max(err) <= 0.1, err      # bf16 operands: see test_gpu_lowprec
+            else:
+                assert torch.equal(out[0], first[0]) and torch.equal(out[1], first[1]), grid
+    finally:
+        op.close()
+
+
+def test_register_direct_batch_schedule_any_grid(M):
+    """The same for the batch kernel over the turbine-like degrees (N = 7, 5, 3)."""
+    import torch
+    specs = [W.make_annulus(7, 48, 4, seed=31, precision=W.FP32, name="a7"),
+             W.make_annulus(5, 40, 3, seed=32, precision=W.FP32, name="a5"),
+             W.make_plane(3, 33, 3, physics=W.NS, riemann=W.ROE, mu=1e-4, precision=W.FP32,
+                          scramble_seed=5, extra_cols=1, name="p3")]
+    inps = [W.make_inputs(s, seed=40 + i, noise=1e-3) for i, s in enumerate(specs)]
+    dins = [H.device_inputs(s, x) for s, x in zip(specs, inps)]
+    disp = [(0.7 + 1.9 * i) * s.l_par for i, s in enumerate(specs)]
+    op = M.MortarOperator(specs)
+    try:
+        op.update(disp)
+        first = None
+        for grid in (8, 11, 24, 0, 600):
+            print(f"[parity] register-direct batch schedule grid {grid}", flush=True)
+            assert M.mortar_set_tuning(op.h, 0, M.KERNEL_REGISTER, 0, grid) == 0
+            outs = H.gpu_flux(op, specs, dins, outs=[H.alloc_outputs(s, fill=0.0) for s in specs])
+            fused = op.conservation([o[0] for o in outs], [o[1] for o in outs])
+            passed = op.conservation([o[0].clone() for o in outs], [o[1].clone() for o in outs])
+            for i in range(len(specs)):
+                assert np.all(np.abs(fused[i] - passed[i]) <= 1e-13 * passed[i][:, 2:3] + 1e-300), (grid, i)
+            if first is None:
+                first = outs
+                for i, s in enumerate(specs):
+                    n, sf = O.decompose(disp[i], s.l_par)
+                    ref = H.oracle_flux(s, H.oracle_inputs(s, inps[i]), n, sf)
+                    err = H.rel_err(s, (outs[i][0].cpu().numpy(), outs[i][1].cpu().numpy()), ref)
+                    assert np.max(err) <= H.TOL[W.FP32], (s.name, err)
+            else:
+                for i in range(len(specs)):
+                    assert torch.equal(outs[i][0], first[i][0]) and torch.equal(outs[i][1], first[i][1]), (grid, i)
+    finally:
+        op.close()
+
+
 @pytest.mark.parametrize("variant", [0, 2])
 def test_prepared_stage_equals_separate_calls(M, variant):
     """MortarStage (arguments marshalled once) gives bitwise the fluxes and conservation
