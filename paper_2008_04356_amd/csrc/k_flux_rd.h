@@ -403,9 +403,15 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
         if (jt < 0) jt += np_;
         return a.fid_m[(size_t)g.row * np_ + jt];
     };
-    auto fetch_s = [&](const TileGeom &g, int cs_) {
-        const uint32_t cs = (uint32_t)cs_, line = (uint32_t)(NP * g.pp);
-        uint32_t os[LF];
+    // The loads of a tile are issued in the order of their first use: both sides'
+    // states and the metrics, then the static and the moving gradients.  Vector-memory
+    // loads complete in issue order, so the projections of the states and the convective
+    // flux wait only for the first of them.  (Issuing the moving gradients only after
+    // the convective flux, which keeps fewer loads outstanding than the wave's counter
+    // holds, left their latency exposed and was slower.)
+    uint32_t os[LF], om[LM];
+    auto offsets = [&](const TileGeom &g, int cs_, int cm_) {
+        const uint32_t cs = (uint32_t)cs_, cm = (uint32_t)cm_, line = (uint32_t)(NP * g.pp);
 #pragma unroll
         for (int ks = 0; ks < KSF; ++ks)
 #pragma unroll
@@ -414,17 +420,6 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
                 os[ks * E + e] = ((line + (j < NP ? j : 0)) * (uint32_t)a.nfs + cs) * (uint32_t)sizeof(T);
             }
 #pragma unroll
-        for (int v = 0; v < VS; ++v) {
-            const buf_rsrc_t &rs = v < 5 ? rU_s : (v < V ? rG_s : rMet);
-            const int pv = v < 5 ? v : (v < V ? v - 5 : v - V);
-#pragma unroll
-            for (int q = 0; q < LF; ++q) ls[v][q] = buf_load<T>(rs, os[q], (int)((uint32_t)pv * (uint32_t)pbytes_s));
-        }
-    };
-    auto fetch_m = [&](const TileGeom &g, int cm_) {
-        const uint32_t cm = (uint32_t)cm_, line = (uint32_t)(NP * g.pp);
-        uint32_t om[LM];
-#pragma unroll
         for (int ks = 0; ks < KSM; ++ks)
 #pragma unroll
             for (int e = 0; e < E; ++e) {
@@ -432,8 +427,19 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
                 const int j = k < NP ? k : (k < 2 * NP ? k - NP : 0);
                 om[ks * E + e] = ((line + j) * (uint32_t)a.nfm + cm) * (uint32_t)sizeof(T);
             }
+    };
+    auto fetch_s = [&](int v0, int v1) {
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
+        for (int v = v0; v < v1; ++v) {
+            const buf_rsrc_t &rs = v < 5 ? rU_s : (v < V ? rG_s : rMet);
+            const int pv = v < 5 ? v : (v < V ? v - 5 : v - V);
+#pragma unroll
+            for (int q = 0; q < LF; ++q) ls[v][q] = buf_load<T>(rs, os[q], (int)((uint32_t)pv * (uint32_t)pbytes_s));
+        }
+    };
+    auto fetch_m = [&](int v0, int v1) {
+#pragma unroll
+        for (int v = v0; v < v1; ++v) {
             const buf_rsrc_t &rs = v < 5 ? rU_m : rG_m;
             const int pv = v < 5 ? v : v - 5;
 #pragma unroll
@@ -554,8 +560,12 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
         // this tile's columns: the static face of slot col and the moving face of slot
         // col are also the faces this lane writes
         const int oc_s = cs_c, oc_m = cm_c;
-        fetch_s(gc, oc_s);
-        fetch_m(gc, oc_m);
+        offsets(gc, oc_s, oc_m);
+        fetch_s(0, 5);
+        fetch_s(V, VS);
+        fetch_m(0, 5);
+        fetch_s(5, V);
+        fetch_m(5, V);
         // every load of the tile is issued before the first is used
         __builtin_amdgcn_sched_barrier(0);
         if constexpr (LOCKSTEP && kRdPingPong) {
