@@ -53,6 +53,11 @@ typedef _Float16 rd_v4h __attribute__((ext_vector_type(4)));
 // supplies A[l % 16][l / 16] and B[l / 16][l % 16]; 16x16x16 (E = 4) lane l supplies
 // A[l % 16][4 (l / 16) + e] and B[4 (l / 16) + e][l % 16], e = 0..3.  Result: lane l,
 // register r holds D[row(l / 16, r)][l % 16].
+// Mortar nodes of the forward products: the A row R holds the coefficients of node
+// node_of_row(R), chosen so that lane l, register r of a 16-row block gets node
+// l / 16 + 4 r (rd_node) in every mode.  Register r of all lanes then holds nodes
+// 4r .. 4r+3, and a register whose nodes all lie past the 2 NP of a column (N = 3, 4, 5,
+// 8, 9) skips the pointwise flux as a whole.
 template <typename T, int PREC> struct RdOp;
 template <> struct RdOp<float, 0> {
     static constexpr int E = 1, KW = 4;
@@ -64,6 +69,7 @@ template <> struct RdOp<float, 0> {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
     __device__ static __forceinline__ int row(int kq, int r) { return 4 * kq + r; }
+    __device__ static __forceinline__ int node_of_row(int R) { return (R >> 2) + 4 * (R & 3); }
 };
 template <> struct RdOp<double, 0> {
     static constexpr int E = 1, KW = 4;
@@ -75,6 +81,7 @@ template <> struct RdOp<double, 0> {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
     __device__ static __forceinline__ int row(int kq, int r) { return kq + 4 * r; }
+    __device__ static __forceinline__ int node_of_row(int R) { return R; }
 };
 template <> struct RdOp<float, 1> {
     static constexpr int E = 4, KW = 16;
@@ -92,6 +99,7 @@ template <> struct RdOp<float, 1> {
         return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
     }
     __device__ static __forceinline__ int row(int kq, int r) { return 4 * kq + r; }
+    __device__ static __forceinline__ int node_of_row(int R) { return (R >> 2) + 4 * (R & 3); }
 };
 template <> struct RdOp<float, 2> {
     static constexpr int E = 4, KW = 16;
@@ -109,7 +117,13 @@ template <> struct RdOp<float, 2> {
         return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
     }
     __device__ static __forceinline__ int row(int kq, int r) { return 4 * kq + r; }
+    __device__ static __forceinline__ int node_of_row(int R) { return (R >> 2) + 4 * (R & 3); }
 };
+
+// Mortar node of lane group kq, register r (within a 16-row block); see RdOp.
+__device__ __forceinline__ int rd_node(int kq, int r) { return kq + 4 * r; }
+// Register r of block rb holds no mortar node of a column (2 NP nodes) in any lane.
+template <int NP> __host__ __device__ constexpr bool rd_idle(int rb, int r) { return 16 * rb + 4 * r >= 2 * NP; }
 
 template <int NP, bool NSV, bool MET, int KW, int WV>
 struct RdCfg {
@@ -284,7 +298,7 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
     op_t Afs[RB][KSF], Afm[RB][KSM], Abs[KSB], Abm[KSB];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
-        const int row = 16 * rb + col;       // A row of this lane
+        const int row = 16 * rb + Op::node_of_row(col);   // node of this lane's A row
 #pragma unroll
         for (int ks = 0; ks < KSF; ++ks) {
             T x[4] = {0, 0, 0, 0};
@@ -328,7 +342,7 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
         for (int e = 0; e < E; ++e) {
             int rb, r;
             bsrc(kb, e, rb, r);
-            const int rho = 16 * rb + Op::row(kq, r);
+            const int rho = 16 * rb + rd_node(kq, r);
             if (col < NP && rho < 2 * NP) {
                 const int k = rho < NP ? 0 : 1;
                 const int q = rho - k * NP;
@@ -354,7 +368,7 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int rho = 16 * rb + Op::row(kq, r);
+            const int rho = 16 * rb + rd_node(kq, r);
             rrow[rb][r] = rho;
             cw[rb][r] = rho < NP ? a.s * wq[rho] : (rho < 2 * NP ? (1.0 - a.s) * wq[rho - NP] : 0.0);
         }
@@ -626,6 +640,11 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
+                if (rd_idle<NP>(rb, r)) {            // no mortar node in any lane
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) FR[v][rb][r] = T(0);
+                    continue;
+                }
                 T UL[5], UR[5], F[5], nx, ny, nz;
 #pragma unroll
                 for (int v = 0; v < 5; ++v) {
@@ -656,6 +675,7 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
                 for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
+                        if (rd_idle<NP>(rb, r)) continue;
                         T U[5], G[15], Fv[5], nx, ny, nz;
 #pragma unroll
                         for (int v = 0; v < 5; ++v) U[v] = T(sd == 0 ? QL[v][rb][r] : QR[v][rb][r]);
