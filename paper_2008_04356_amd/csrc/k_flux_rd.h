@@ -329,7 +329,9 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
             else Afm[rb][ks] = Op::pack(f);
         }
     }
-    // back projection: A[j = col][rho], rho = mortar-node row supplied in K step kb
+    // back projection: A row R = col holds face node j = node_of_row(col) (so that lane
+    // group kq, register r of the result holds face node rd_node(kq, r)); column rho =
+    // the mortar node supplied in K step kb
     auto bsrc = [&](int kb, int e, int &rb, int &r) {
         rb = E == 1 ? kb / 4 : kb;
         r = E == 1 ? kb % 4 : e;
@@ -343,11 +345,12 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
             int rb, r;
             bsrc(kb, e, rb, r);
             const int rho = 16 * rb + rd_node(kq, r);
-            if (col < NP && rho < 2 * NP) {
+            const int jn = Op::node_of_row(col);
+            if (jn < NP && rho < 2 * NP) {
                 const int k = rho < NP ? 0 : 1;
                 const int q = rho - k * NP;
-                xs[e] = mats[4 * NN + k * NN + col * NP + q];
-                xm[e] = mats[4 * NN + (2 + k) * NN + col * NP + q];
+                xs[e] = mats[4 * NN + k * NN + jn * NP + q];
+                xm[e] = mats[4 * NN + (2 + k) * NN + jn * NP + q];
             }
             fs[e] = (float)xs[e];
             fm[e] = (float)xm[e];
@@ -375,7 +378,7 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
     double wj[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int j = Op::row(kq, r);
+        const int j = rd_node(kq, r);
         wj[r] = j < NP ? wq[j] : 0.0;
     }
     // conservation partials written with the fluxes in the 4-byte modes (the FP64
@@ -770,6 +773,7 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
                     }
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
+                    if (4 * r >= NP) continue;             // no face node in any lane
                     As += wj[r] * (double)ds[r];
                     Am += wj[r] * (double)dm[r];
                 }
@@ -791,6 +795,7 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
                 double ts = 0.0, tm = 0.0, ms = 0.0, mm = 0.0;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
+                    if (4 * r >= NP) continue;
                     const double ys = out_s ? wj[r] * (double)T(ds[r]) : 0.0;
                     const double ym = out_m ? wj[r] * (double)T(dm[r]) : 0.0;
                     ts += ys;
@@ -809,7 +814,8 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
             // of them before the next); masked lanes get an offset beyond the array
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int j = Op::row(kq, r);
+                if (4 * r >= NP) continue;                 // no face node in any lane
+                const int j = rd_node(kq, r);
                 const uint32_t jj = (uint32_t)min(j, NP - 1);
                 const uint32_t o_s = ((line + jj) * (uint32_t)a.nfs + (uint32_t)oc_s) * (uint32_t)sizeof(T) +
                                      (uint32_t)v * (uint32_t)pbytes_s;
