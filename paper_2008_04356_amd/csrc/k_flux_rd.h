@@ -603,6 +603,7 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
+                    if (rd_idle<NP>(rb, r)) continue;
                     T nx = MT[0][rb][r], ny = MT[1][rb][r], nz = MT[2][rb][r];
                     unit_normal(nx, ny, nz);
                     MT[0][rb][r] = nx;
@@ -701,6 +702,7 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
+                if (rd_idle<NP>(rb, r)) continue;          // already zero
                 T dS = a.dS;
                 if constexpr (MET) dS = MT[3][rb][r];
 #pragma unroll
@@ -721,6 +723,10 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
+                    if (rd_idle<NP>(rb, r)) {
+                        FM[rb][r] = T(0);
+                        continue;
+                    }
                     const T nxt = rd_right(FR[v][rb][r]);
                     FM[rb][r] = rrow[rb][r] < NP ? nxt : FR[v][rb][r];
                 }
@@ -736,6 +742,7 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
             acc_t ds = {0, 0, 0, 0}, dm = {0, 0, 0, 0};
 #pragma unroll
             for (int kb = 0; kb < KSB; ++kb) {
+                if (E == 1 && rd_idle<NP>(kb / 4, kb % 4)) continue;   // a zero B operand
                 T xs[4], xm[4];
                 float fs[4], fm[4];
 #pragma unroll
