@@ -73,7 +73,9 @@ def copy_calibration(mb):
 
 
 TRAFFIC_PROFILES = {2: "profiles/k_mortar_flux_ns_n5_plane128x64_traffic.md",
-                    4: "profiles/k_mortar_flux_rd_batch_turbine_c4_traffic.md"}
+                    3: "profiles/k_mortar_flux_rd_annulus_n7_512x64.md",
+                    4: "profiles/k_mortar_flux_rd_batch_turbine_c4_traffic.md",
+                    5: "profiles/k_mortar_flux_rd_euler_plane_n9_256x256.md"}
 
 
 def sources_sha256(names):
