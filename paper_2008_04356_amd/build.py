@@ -21,7 +21,8 @@ SOURCES = ["mortar_capi.hip", "k_topology.hip", "k_flux_f32.hip", "k_flux_f64.hi
            "k_flux_rd_f32.hip", "k_flux_rd_f64.hip", "k_flux_rd_bf16.hip",
            "k_flux_rd_fp16.hip", "k_flux_rd_batch_f32.hip",
            "k_flux_mfma_f32.hip", "k_flux_mfma_f64.hip", "k_flux_batch_f32.hip",
-           "k_flux_batch_f64.hip", "k_flux_hi_f32.hip", "k_flux_hi_f64.hip", "k_lift_hi.hip"]
+           "k_flux_batch_f64.hip", "k_flux_hi_f32.hip", "k_flux_hi_f64.hip", "k_lift_hi.hip",
+           "k_lift_rd_f32.hip"]
 
 CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -34,7 +35,7 @@ CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 # this compiler option makes the compiler itself crash.
 EXTRA = {s: ["-mllvm", "-amdgpu-mfma-vgpr-form"]
          for s in ("k_flux_rd_f32.hip", "k_flux_rd_bf16.hip", "k_flux_rd_fp16.hip",
-                   "k_flux_rd_batch_f32.hip", "k_flux_hyb_f32.hip")}
+                   "k_flux_rd_batch_f32.hip", "k_flux_hyb_f32.hip", "k_lift_rd_f32.hip")}
 
 
 def _compile(src):

@@ -138,8 +138,6 @@ struct RdCfg {
     static constexpr int NT = 64 * WAVES;
 };
 
-// Output faces per tile of the register-direct kernel (16 slots, one is the halo).
-constexpr int kRdTileFaces = 15;
 
 // Value of lane - 1 (rd_left) or lane + 1 (rd_right) within each row of 16 lanes; the
 // lane at the row's edge receives 0.
@@ -268,10 +266,16 @@ struct WaveCursor {
 // its own LDS slots (acc, [20][NT] doubles), and at the end of the interface the
 // workgroup adds its lanes' slots in a fixed order (red: 320 doubles of scratch) into
 // a.cons (layout of FluxArgs).
-template <typename T, int NP, bool NSV, bool MET, int RIEM, int PREC, int WV>
+// LIFT: the BR1 lifting surface term instead of the flux (Euler-shaped: states and
+// metrics in, no gradients): at every mortar node the average of both sides' states times
+// each component of the static unit normal and the surface element, 15 values
+// (component d, variable v at plane 5 d + v) back-projected onto both sides.
+template <typename T, int NP, bool NSV, bool MET, int RIEM, int PREC, int WV, bool LIFT = false>
 __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work, T *mats, double *wq,
                                              double *acc, double *red)
 {
+    static_assert(!LIFT || (!NSV && PREC == 0), "lifting: states only, element-type products");
+    constexpr int NOUT = LIFT ? 15 : 5;      // output planes per side
     using Op = RdOp<T, PREC>;
     using C = RdCfg<NP, NSV, MET, Op::KW, WV>;
     using op_t = typename Op::op_t;
@@ -383,7 +387,7 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
     }
     // conservation partials written with the fluxes in the 4-byte modes (the FP64
     // kernel's registers are already spent: its partials come from a pass)
-    constexpr bool FUSE = sizeof(T) == 4;
+    constexpr bool FUSE = sizeof(T) == 4 && !LIFT;
     if constexpr (FUSE) {
 #pragma unroll
         for (int k = 0; k < 20; ++k) acc[k * C::NT + tid] = 0.0;
@@ -399,8 +403,8 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
     const buf_rsrc_t rG_s = buf_rsrc(a.Gs, NSV ? 15u * (uint32_t)pbytes_s : 0u);
     const buf_rsrc_t rG_m = buf_rsrc(a.Gm, NSV ? 15u * (uint32_t)pbytes_m : 0u);
     const buf_rsrc_t rMet = buf_rsrc(a.met, MET ? 4u * (uint32_t)pbytes_s : 0u);
-    const buf_rsrc_t rF_s = buf_rsrc(a.Fs, 5u * (uint32_t)pbytes_s);
-    const buf_rsrc_t rF_m = buf_rsrc(a.Fm, 5u * (uint32_t)pbytes_m);
+    const buf_rsrc_t rF_s = buf_rsrc(a.Fs, (uint32_t)NOUT * (uint32_t)pbytes_s);
+    const buf_rsrc_t rF_m = buf_rsrc(a.Fm, (uint32_t)NOUT * (uint32_t)pbytes_m);
 
     // ---- per-tile operand fetch ---------------------------------------------------
     // One 32-bit byte offset per K value, shared by all variables (the variable's plane
@@ -638,8 +642,29 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
         // mortar, columns past the tile) hold values that may be anything, even
         // non-finite; their fluxes are replaced by exact zeros below, and no other row or
         // column ever reads them.
-        T FR[5][RB][4];
+        T FR[NOUT][RB][4];
         T Fprev[5] = {0, 0, 0, 0, 0};
+        if constexpr (LIFT) {
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (rd_idle<NP>(rb, r)) {
+#pragma unroll
+                        for (int o = 0; o < NOUT; ++o) FR[o][rb][r] = T(0);
+                        continue;
+                    }
+                    T n[3], dS = a.dS;
+                    normal(rb, r, n[0], n[1], n[2]);
+                    if constexpr (MET) dS = MT[3][rb][r];
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) {
+                        const T avg = use[rb][r] ? T(0.5) * (T(QL[v][rb][r]) + T(QR[v][rb][r])) * dS : T(0);
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) FR[5 * d + v][rb][r] = avg * n[d];
+                    }
+                }
+        } else {
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
@@ -708,6 +733,7 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
 #pragma unroll
                 for (int v = 0; v < 5; ++v) FR[v][rb][r] = use[rb][r] ? FR[v][rb][r] * dS : T(0);
             }
+        }   // flux (not LIFT)
 
         // ---- back projection onto both sides ----------------------------------------
         const bool out_s = live_tile && col >= 1 && col <= gc.nf;   // static face i0-1+col
@@ -715,7 +741,7 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
         const double wpp = FUSE ? wq[gc.pp] : 0.0;                 // weight of the line
         const uint32_t line = (uint32_t)(NP * gc.pp);
 #pragma unroll
-        for (int v = 0; v < 5; ++v) {
+        for (int v = 0; v < NOUT; ++v) {
             // moving face of slot col: lower part = mortar (i0-1+col, 1) of this column,
             // upper part = mortar (i0+col, 0) of the next column
             T FM[RB][4];
@@ -855,6 +881,18 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
     }
 }
 
+// The BR1 lifting surface term through the register-direct body (four free waves).
+template <typename T, int NP, bool MET>
+__global__ __launch_bounds__(256) void k_mortar_lift_rd(FluxArgs<T> a)
+{
+    __shared__ double work[assemble_scratch<NP>()];
+    __shared__ T mats[8 * NP * NP];
+    __shared__ double wq[NP];
+    __shared__ double acc[1];
+    __shared__ double red[1];
+    rd_interface<T, NP, false, MET, 0, 0, 4, true>(a, work, mats, wq, acc, red);
+}
+
 template <typename T, int NP, bool NSV, bool MET, int RIEM, int PREC>
 __global__ __launch_bounds__(64 * rd_waves((int)sizeof(T), NSV)) void k_mortar_flux_rd(FluxArgs<T> a)
 {
@@ -935,6 +973,24 @@ static hipError_t rd_pick(const FluxArgs<T> &a, int grid, bool ns, bool met, int
                          : rd_go<T, NP, false, true, 0, PREC>(a, grid, st);
     return riem ? rd_go<T, NP, false, false, 1, PREC>(a, grid, st)
                 : rd_go<T, NP, false, false, 0, PREC>(a, grid, st);
+}
+
+template <typename T, int NP>
+static hipError_t rd_lift_go(const FluxArgs<T> &a, int grid, bool met, hipStream_t st)
+{
+    if (met) hipLaunchKernelGGL((k_mortar_lift_rd<T, NP, true>), dim3(grid), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_mortar_lift_rd<T, NP, false>), dim3(grid), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+template <typename T, int NP>
+static int rd_lift_occ(bool met)
+{
+    int nb = 0;
+    const void *k = met ? reinterpret_cast<const void *>(&k_mortar_lift_rd<T, NP, true>)
+                        : reinterpret_cast<const void *>(&k_mortar_lift_rd<T, NP, false>);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 256, 0) != hipSuccess) return 1;
+    return nb > 0 ? nb : 1;
 }
 
 template <typename T, int NP, int PREC>

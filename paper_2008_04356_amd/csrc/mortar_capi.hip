@@ -29,6 +29,8 @@ int flux_hyb_occupancy_f32(int NP, bool ns, bool met, int riem);
 int lift_occupancy(int NP, bool met, bool f64);
 int lift_tile_capacity(int NP, bool met, bool f64);
 hipError_t launch_lift_f32(const FluxArgs<float> &a, int NP, int grid, bool met, hipStream_t st);
+int lift_rd_occupancy_f32(int NP, bool met);
+hipError_t launch_lift_rd_f32(const FluxArgs<float> &a, int NP, int grid, bool met, hipStream_t st);
 hipError_t launch_lift_f64(const FluxArgs<double> &a, int NP, int grid, bool met, hipStream_t st);
 int flux_hyb_tile_capacity_f32(int NP, bool ns, bool met);
 hipError_t launch_flux_hyb_f32(const FluxArgs<float> &a, int NP, int grid, bool ns, bool met,
@@ -683,6 +685,24 @@ int mortar_lifting(mortar_handle *h, const void *const *U_s, const void *const *
     for (size_t i = 0; i < h->ifs.size(); ++i) {
         const Iface &f = h->ifs[i];
         const bool met = f.d_metrics != nullptr, f64 = f.elem == 8;
+        if (!f64 && f.d.N <= 5) {
+            // FP32 up to degree 5: the register-direct body (one wave per 15-face tile);
+            // plane N = 5, 128x64: 18.8 us against 25.6 us for the VALU kernel.  At
+            // degree 7 it holds more registers (two waves per SIMD) and loses (annulus
+            // N = 7, 512x64: 165 us against 143 us); degrees 6 and up keep the VALU
+            // kernel.
+            const int tiles_per_row = (f.d.n_par + kRdTileFaces - 1) / kRdTileFaces;
+            const int tile_len = (f.d.n_par + tiles_per_row - 1) / tiles_per_row;
+            const int n_tiles = tiles_per_row * f.NP * f.d.n_perp;
+            const int grid = std::max(8, std::min((n_tiles + 3) / 4, lift_rd_occupancy_f32(f.NP, met) * h->n_cu));
+            FluxArgs<float> a;
+            int nt = 0;
+            fill_args(f, U_s[i], U_m[i], nullptr, nullptr, L_s[i], L_m[i], a, nt);
+            a.tiles_per_row = tiles_per_row; a.tile_len = tile_len; a.n_tiles = n_tiles;
+            a.cons = nullptr;
+            TRY_HIP(launch_lift_rd_f32(a, f.NP, grid, met, st));
+            continue;
+        }
         // tiles of the lifting kernel's capacity, balanced along the row (fill_args uses
         // the flux launch's tuning, so the fields are set here)
         const int cap = lift_tile_capacity(f.NP, met, f64);
@@ -1267,7 +1287,7 @@ void fill_args(const Iface &f, const void *Us, const void *Um, const void *Gs,
     const int64_t np = f.d.n_par;
     int cap = f.flux_variant == 3 ? flux_wide_tile_capacity_f32(f.NP, ns, met)
             : f.flux_variant == 4 ? flux_hyb_tile_capacity_f32(f.NP, ns, met)
-            : f.flux_variant != 0 ? 15
+            : f.flux_variant != 0 ? kRdTileFaces
             : (f.elem == 8 ? flux_tile_capacity_f64(f.NP, ns, met)
                            : flux_tile_capacity_f32(f.NP, ns, met));
     if (f.tune_tile > 0) cap = std::min(cap, f.tune_tile);

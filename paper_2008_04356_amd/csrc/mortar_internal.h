@@ -163,6 +163,8 @@ constexpr int kRdBatchWaves = kRdLockWaves;
 // Largest array (bytes) the register-direct kernels address with 32-bit buffer offsets;
 // offsets from there up to 4 GiB mark masked-off lanes.
 constexpr int64_t kRdMaxBytes = 0xFFFFFF00;
+// Output faces per tile of the register-direct kernels (16 slots, one is the halo).
+constexpr int kRdTileFaces = 15;
 hipError_t launch_conservation_final(const Iface &f, double *d_out, hipStream_t st);
 constexpr int kMaxConsBatch = 8;
 hipError_t launch_conservation_final_batch(const Iface *const *fs, double *const *outs, int n,
