@@ -1,7 +1,8 @@
 """GPU: the BR1 lifting surface term (mortar_lifting) against the FP64 oracle, element
 by element per output plane (3 normal components x 5 variables), at sizes that span
-several tiles and a ragged tail, with per-point metrics, over degrees 1-15, and the
-plane N=5 workload's shape at full size, every row."""
+several tiles and a ragged tail, with per-point metrics, over degrees 1-15 (FP32 up to
+degree 5 runs the register-direct lifting body, the rest the VALU lifting kernel), tiny
+periodic rows, and the plane N=5 workload's shape at full size, every row."""
 import numpy as np
 import pytest
 
@@ -92,6 +93,23 @@ def test_degrees(M, N, node_set):
     spec = W.make_plane(N, 23, 2, physics=W.EULER, riemann=W.ROE, node_set=node_set,
                         precision=W.FP32, scramble_seed=N, extra_cols=1)
     _case(M, spec, [0.41 * spec.l_par, 5.003 * spec.l_par], seed=N)
+
+
+@pytest.mark.parametrize("n_par", [1, 2, 3, 16])
+def test_tiny_and_single_tile_rows(M, n_par):
+    """Rows of 1-3 faces (a tile wraps around the periodic row) and of one tile plus one
+    face, FP32 degree 3: the register-direct lifting body."""
+    spec = W.make_plane(3, n_par, 3, physics=W.NS, riemann=W.ROE, mu=1e-3, precision=W.FP32,
+                        scramble_seed=n_par, extra_cols=1)
+    _case(M, spec, [0.3 * spec.l_par, 2.7 * spec.l_par, 41.05 * spec.l_par], seed=n_par)
+
+
+@pytest.mark.parametrize("N", [3, 5, 6])
+def test_annulus_metrics_fp32_degrees(M, N):
+    """Per-point metrics in FP32 on both sides of the kernel choice: register-direct up to
+    degree 5, the VALU lifting kernel from degree 6."""
+    spec = W.make_annulus(N, 37, 3, seed=N, precision=W.FP32)
+    _case(M, spec, [0.2 * spec.l_par, 9.7 * spec.l_par], seed=N)
 
 
 def test_plane_workload_full_size_all_rows(M):
