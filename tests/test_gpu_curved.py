@@ -2,7 +2,7 @@
 polynomial face geometry, per-point static metrics whose normal turns along the slide)
 against the FP64 oracle: the flux in every launch variant, over degrees, the BR1 lifting
 term, a batch of curved and flat interfaces in one launch, the bf16/fp16 modes, and the
-full-size curved workloads on sampled rows."""
+full-size curved workloads on every row."""
 import math
 
 import numpy as np
