@@ -31,6 +31,8 @@
 // integrals (discrete conservation, Sec. 3.2) up to FP32 storage rounding.
 #pragma once
 
+#include <type_traits>
+
 #include "assemble.h"
 #include "flux_physics.h"
 #include "k_flux.h"
@@ -256,6 +258,41 @@ struct WaveCursor {
     __device__ bool round_valid(int wave) const { return k - wave < limit; }
     __device__ int tile() const { return k; }
     __device__ void next() { k += stride; }
+};
+
+// The wave cursor of the out-of-phase lockstep groups: each XCD's eighth of the tiles is
+// cut in two halves, the first group (waves 0 .. waves/2 - 1) takes the first half and the
+// second group the second, so that the two groups, which run half a round apart, share
+// no cache lines except where the halves meet.  A round is run while the first group's
+// first wave has a tile (the first half is never the shorter), the same answer for every
+// wave of the workgroup.
+struct HalfCursor {
+    int k, limit, stride, first, first_limit;
+    __device__ HalfCursor(int n, int waves, int wave)
+    {
+        const int g = gridDim.x;
+        const int xcd = blockIdx.x % kXcds;
+        const int nwg = g / kXcds + ((g % kXcds) > xcd ? 1 : 0);
+        const int per = (n + kXcds - 1) / kXcds;
+        const int base = min(n, xcd * per);
+        const int lim = min(n, base + per);
+        const int mid = base + (lim - base + 1) / 2;
+        const int hw = waves / 2;
+        const int grp = wave < hw ? 0 : 1;
+        stride = nwg * hw;
+        first = base + (blockIdx.x / kXcds) * hw;
+        first_limit = mid;
+        k = (grp ? mid : base) + (blockIdx.x / kXcds) * hw + (wave - grp * hw);
+        limit = grp ? lim : mid;
+    }
+    __device__ bool valid() const { return k < limit; }
+    __device__ bool round_valid(int) const { return first < first_limit; }
+    __device__ int tile() const { return k; }
+    __device__ void next()
+    {
+        k += stride;
+        first += stride;
+    }
 };
 
 // One interface: every workgroup assembles the stage's matrices, then its waves take
@@ -557,7 +594,8 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
     // wave per SIMD in FP64, or the fp16 scaling's cross-lane reductions, the barrier cost
     // more than the fetches it saves).
     constexpr bool LOCKSTEP = rd_lockstep((int)sizeof(T), NSV);
-    WaveCursor cur(a.n_tiles, C::WAVES, wave);
+    using Cursor = std::conditional_t<LOCKSTEP && kRdPingPong && kRdSplitHalves, HalfCursor, WaveCursor>;
+    Cursor cur(a.n_tiles, C::WAVES, wave);
     bool more = LOCKSTEP ? cur.round_valid(wave) : cur.valid();
     bool mine = cur.valid();
     TileGeom g = tile_geom(a, mine ? cur.tile() : 0, NP);

@@ -156,6 +156,8 @@ constexpr int kRdLockWaves = 8;
 // overlaps the other group's arithmetic on the same CU, where one barrier for all would
 // have every wave of the CU wait for memory at once.
 constexpr bool kRdPingPong = true;
+// The two groups take tiles from the two halves of each XCD's share (HalfCursor).
+constexpr bool kRdSplitHalves = true;
 __host__ __device__ constexpr bool rd_lockstep(int elem_bytes, bool ns) { return ns && elem_bytes == 4; }
 __host__ __device__ constexpr int rd_waves(int elem_bytes, bool ns) { return rd_lockstep(elem_bytes, ns) ? kRdLockWaves : 4; }
 // the batch kernel (4-byte data, both physics)
