@@ -593,7 +593,7 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
     // lines in flight exceed the L2); the other launches run their waves freely (with one
     // wave per SIMD in FP64, or the fp16 scaling's cross-lane reductions, the barrier cost
     // more than the fetches it saves).
-    constexpr bool LOCKSTEP = rd_lockstep((int)sizeof(T), NSV);
+    constexpr bool LOCKSTEP = rd_lockstep((int)sizeof(T), NSV, NP) && !LIFT;
     using Cursor = std::conditional_t<LOCKSTEP && kRdPingPong && kRdSplitHalves, HalfCursor, WaveCursor>;
     Cursor cur(a.n_tiles, C::WAVES, wave);
     bool more = LOCKSTEP ? cur.round_valid(wave) : cur.valid();
@@ -932,9 +932,9 @@ __global__ __launch_bounds__(256) void k_mortar_lift_rd(FluxArgs<T> a)
 }
 
 template <typename T, int NP, bool NSV, bool MET, int RIEM, int PREC>
-__global__ __launch_bounds__(64 * rd_waves((int)sizeof(T), NSV)) void k_mortar_flux_rd(FluxArgs<T> a)
+__global__ __launch_bounds__(64 * rd_waves((int)sizeof(T), NSV, NP)) void k_mortar_flux_rd(FluxArgs<T> a)
 {
-    constexpr int WV = rd_waves((int)sizeof(T), NSV);
+    constexpr int WV = rd_waves((int)sizeof(T), NSV, NP);
     constexpr int NT = 64 * WV;
     __shared__ double work[assemble_scratch<NP>()];
     __shared__ T mats[8 * NP * NP];          // Pf[4][NP][NP], Pb[4][NP][NP]
@@ -980,7 +980,7 @@ namespace mortar {
 template <typename T, int NP, bool NSV, bool MET, int RIEM, int PREC>
 static hipError_t rd_go(const FluxArgs<T> &a, int grid, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_mortar_flux_rd<T, NP, NSV, MET, RIEM, PREC>), dim3(grid), dim3(64 * rd_waves((int)sizeof(T), NSV)), 0,
+    hipLaunchKernelGGL((k_mortar_flux_rd<T, NP, NSV, MET, RIEM, PREC>), dim3(grid), dim3(64 * rd_waves((int)sizeof(T), NSV, NP)), 0,
                        st, a);
     return hipGetLastError();
 }
@@ -990,7 +990,7 @@ static int rd_occ1()
 {
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &nb, reinterpret_cast<const void *>(&k_mortar_flux_rd<T, NP, NSV, MET, RIEM, PREC>), 64 * rd_waves((int)sizeof(T), NSV),
+            &nb, reinterpret_cast<const void *>(&k_mortar_flux_rd<T, NP, NSV, MET, RIEM, PREC>), 64 * rd_waves((int)sizeof(T), NSV, NP),
             0) != hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;

@@ -1319,7 +1319,7 @@ void fill_args(const Iface &f, const void *Us, const void *Um, const void *Gs,
 static int rd_grid_of(const Iface &f, int n_cu, int nt)
 {
     if (f.tune_grid > 0) return std::max(8, f.tune_grid);
-    const int w = rd_waves((int)f.elem, f.d.physics == MORTAR_NAVIER_STOKES);
+    const int w = rd_waves((int)f.elem, f.d.physics == MORTAR_NAVIER_STOKES, f.NP);
     return std::max(8, std::min((nt + w - 1) / w, f.flux_occ * n_cu));
 }
 

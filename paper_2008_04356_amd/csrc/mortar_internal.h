@@ -140,13 +140,16 @@ int cons_blocks(int P, int nfaces);
 // Largest flux grid whose workgroups write conservation partials.
 constexpr int kConsGridMax = 4096;
 // Waves of a register-direct workgroup; they take consecutive tiles of one line.  In the
-// Navier-Stokes launches with 4-byte data they start each round of tiles together (a
-// workgroup barrier per round), so the cache lines that neighbouring tiles share (a tile's
-// 16 face slots span 64 bytes of each 128-byte line of a (variable, node) row, and
-// consecutive tiles overlap by the halo face) are requested by several waves of one CU at
-// about the same time and fetched from HBM once: eight waves (two per SIMD, the occupancy
-// of those launches).  The other launches run four independent waves per workgroup (the
-// finer granularity keeps their higher occupancy).
+// lockstep launches (4-byte data: Navier-Stokes, and Euler from kRdLockEulerNP nodes per
+// line on) they go through the rounds of tiles together (a workgroup barrier per round),
+// so the cache lines that neighbouring tiles share (a tile's 16 face slots span 64 bytes
+// of each 128-byte line of a (variable, node) row, and consecutive tiles overlap by the
+// halo face) are requested by several waves of one CU at about the same time: fetched
+// from HBM once, and written back once when their two halves come from two tiles.  Eight
+// waves (two per SIMD, the occupancy of those launches).  The other launches run four
+// independent waves per workgroup (the finer granularity keeps their higher occupancy,
+// three or four waves per SIMD, which an eight-wave workgroup with its 80 KB of
+// conservation slots would lose).
 constexpr int kRdLockWaves = 8;
 // The lockstep waves go in two groups out of phase: waves WV/2.. meet at the top of a
 // round, waves 0..WV/2-1 after issuing the round's loads.  A barrier then releases the
@@ -158,8 +161,18 @@ constexpr int kRdLockWaves = 8;
 constexpr bool kRdPingPong = true;
 // The two groups take tiles from the two halves of each XCD's share (HalfCursor).
 constexpr bool kRdSplitHalves = true;
-__host__ __device__ constexpr bool rd_lockstep(int elem_bytes, bool ns) { return ns && elem_bytes == 4; }
-__host__ __device__ constexpr int rd_waves(int elem_bytes, bool ns) { return rd_lockstep(elem_bytes, ns) ? kRdLockWaves : 4; }
+// Euler launches with 4-byte data run in lockstep from this many nodes per line on (N = 7:
+// two waves per SIMD already; plane N = 9 Euler: 253 -> 223 us in FP32, reads 1.14x ->
+// 1.01x and writes 1.35x -> 1.02x the algorithmic bytes).
+constexpr int kRdLockEulerNP = 8;
+__host__ __device__ constexpr bool rd_lockstep(int elem_bytes, bool ns, int np)
+{
+    return elem_bytes == 4 && (ns || np >= kRdLockEulerNP);
+}
+__host__ __device__ constexpr int rd_waves(int elem_bytes, bool ns, int np)
+{
+    return rd_lockstep(elem_bytes, ns, np) ? kRdLockWaves : 4;
+}
 // the batch kernel (4-byte data, both physics)
 constexpr int kRdBatchWaves = kRdLockWaves;
 // Largest array (bytes) the register-direct kernels address with 32-bit buffer offsets;
