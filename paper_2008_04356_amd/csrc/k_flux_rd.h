@@ -585,14 +585,15 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
     // current one, before its loads: vector-memory operations complete in issue order,
     // so the current tile's loads (waited for anyway) retire the lookup, while a lookup
     // issued after the previous tile's stores would also wait for them.
-    // Navier-Stokes in 4-byte data: the waves of the workgroup go through the rounds of
-    // tiles together: every wave runs every round (a wave without a tile in the last round
-    // computes tile 0 and stores nothing), and one barrier per round and wave keeps them
-    // together, in two groups out of phase (kRdPingPong).  This fetches the lines
-    // neighbouring tiles share once (the gradients make these launches the ones whose
-    // lines in flight exceed the L2); the other launches run their waves freely (with one
-    // wave per SIMD in FP64, or the fp16 scaling's cross-lane reductions, the barrier cost
-    // more than the fetches it saves).
+    // Lockstep launches (rd_lockstep: 4-byte data, Navier-Stokes, and Euler with enough
+    // nodes per line): the waves of the workgroup go through the rounds of tiles
+    // together: every wave runs every round (a wave without a tile in a round computes
+    // tile 0 and stores nothing), and one barrier per round and wave keeps them together,
+    // in two groups out of phase (kRdPingPong) that take their tiles from the two halves
+    // of the XCD's share (HalfCursor).  This fetches the lines neighbouring tiles share
+    // once and writes back each line once.  The other launches run their waves freely
+    // (FP64 has one or two waves per SIMD and no conservation slots; the smaller Euler
+    // launches keep three or four waves per SIMD in four-wave workgroups).
     constexpr bool LOCKSTEP = rd_lockstep((int)sizeof(T), NSV, NP) && !LIFT;
     using Cursor = std::conditional_t<LOCKSTEP && kRdPingPong && kRdSplitHalves, HalfCursor, WaveCursor>;
     Cursor cur(a.n_tiles, C::WAVES, wave);
