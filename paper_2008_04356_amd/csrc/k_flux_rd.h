@@ -16,9 +16,9 @@
 // fluxes in registers.  The back projection is a GEMM with K = the 2 NP mortar nodes of
 // a column, whose B operand is exactly those flux registers (one more DPP shift for the
 // moving side, whose upper mortar sits in the next column).  After the prologue only the
-// conservation partials of the 4-byte launches go through LDS; in the Navier-Stokes
-// launches with 4-byte data the waves of a workgroup meet at one barrier per round of
-// tiles, so that they fetch the cache lines their neighbouring tiles share together.
+// conservation partials of the 4-byte launches go through LDS; in the lockstep launches
+// (rd_lockstep) the waves of a workgroup meet at one barrier per round of tiles, so that
+// they fetch the cache lines their neighbouring tiles share together.
 //
 // Precision (PREC): 0 runs the GEMMs in the element type (v_mfma_{f32,f64}_16x16x4).
 // 1 / 2 round the GEMM operands to bf16 / fp16 (v_mfma_f32_16x16x16_{bf16,f16}, FP32
@@ -58,8 +58,9 @@ typedef _Float16 rd_v4h __attribute__((ext_vector_type(4)));
 // Mortar nodes of the forward products: the A row R holds the coefficients of node
 // node_of_row(R), chosen so that lane l, register r of a 16-row block gets node
 // l / 16 + 4 r (rd_node) in every mode.  Register r of all lanes then holds nodes
-// 4r .. 4r+3, and a register whose nodes all lie past the 2 NP of a column (N = 3, 4, 5,
-// 8, 9) skips the pointwise flux as a whole.
+// 4r .. 4r+3, and a register whose nodes all lie past the 2 NP of a column (every degree
+// but N = 6 and 7) skips the pointwise flux as a whole; the same holds for the NP face
+// nodes of the back projection's result (its stores and conservation terms).
 template <typename T, int PREC> struct RdOp;
 template <> struct RdOp<float, 0> {
     static constexpr int E = 1, KW = 4;
