@@ -137,7 +137,7 @@ int mortar_flux(mortar_handle *h, const void *const *U_s, const void *const *U_m
  * U_s[i], U_m[i]: states [5][P][n_face] as for mortar_flux; L_s[i], L_m[i]: outputs
  * [3][5][P][n_face] (component d, variable v, as the gradient inputs), the same values
  * on both sides (static normal; the caller applies the sign).  Only the interface's
- * columns are written.  One launch per interface: FP32 element type up to degree 5
+ * columns are written.  One launch per interface: FP32 element type up to degree 9
  * through the register-direct body (projections on the matrix cores in FP32), otherwise
  * the VALU-projection kernel; in the bf16/fp16 modes it runs in FP32 (their element
  * type).  UNSUPPORTED when an output array reaches 2 GiB.  Asynchronous on stream; no allocation.  NOT_READY before

@@ -595,7 +595,7 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
     // once and writes back each line once.  The other launches run their waves freely
     // (FP64 has one or two waves per SIMD and no conservation slots; the smaller Euler
     // launches keep three or four waves per SIMD in four-wave workgroups).
-    constexpr bool LOCKSTEP = rd_lockstep((int)sizeof(T), NSV, NP) && !LIFT;
+    constexpr bool LOCKSTEP = LIFT ? WV == kRdLockWaves : rd_lockstep((int)sizeof(T), NSV, NP);
     using Cursor = std::conditional_t<LOCKSTEP && kRdPingPong && kRdSplitHalves, HalfCursor, WaveCursor>;
     Cursor cur(a.n_tiles, C::WAVES, wave);
     bool more = LOCKSTEP ? cur.round_valid(wave) : cur.valid();
@@ -697,11 +697,13 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
                     T n[3], dS = a.dS;
                     normal(rb, r, n[0], n[1], n[2]);
                     if constexpr (MET) dS = MT[3][rb][r];
+                    // rows that are not needed mortar nodes may hold anything (the unit
+                    // normal of a zero padding row is not finite): selected, not multiplied
 #pragma unroll
                     for (int v = 0; v < 5; ++v) {
-                        const T avg = use[rb][r] ? T(0.5) * (T(QL[v][rb][r]) + T(QR[v][rb][r])) * dS : T(0);
+                        const T avg = T(0.5) * (T(QL[v][rb][r]) + T(QR[v][rb][r])) * dS;
 #pragma unroll
-                        for (int d = 0; d < 3; ++d) FR[5 * d + v][rb][r] = avg * n[d];
+                        for (int d = 0; d < 3; ++d) FR[5 * d + v][rb][r] = use[rb][r] ? avg * n[d] : T(0);
                     }
                 }
         } else {
@@ -923,14 +925,14 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
 
 // The BR1 lifting surface term through the register-direct body (four free waves).
 template <typename T, int NP, bool MET>
-__global__ __launch_bounds__(256) void k_mortar_lift_rd(FluxArgs<T> a)
+__global__ __launch_bounds__(64 * rd_lift_waves(NP)) void k_mortar_lift_rd(FluxArgs<T> a)
 {
     __shared__ double work[assemble_scratch<NP>()];
     __shared__ T mats[8 * NP * NP];
     __shared__ double wq[NP];
     __shared__ double acc[1];
     __shared__ double red[1];
-    rd_interface<T, NP, false, MET, 0, 0, 4, true>(a, work, mats, wq, acc, red);
+    rd_interface<T, NP, false, MET, 0, 0, rd_lift_waves(NP), true>(a, work, mats, wq, acc, red);
 }
 
 template <typename T, int NP, bool NSV, bool MET, int RIEM, int PREC>
@@ -1018,8 +1020,8 @@ static hipError_t rd_pick(const FluxArgs<T> &a, int grid, bool ns, bool met, int
 template <typename T, int NP>
 static hipError_t rd_lift_go(const FluxArgs<T> &a, int grid, bool met, hipStream_t st)
 {
-    if (met) hipLaunchKernelGGL((k_mortar_lift_rd<T, NP, true>), dim3(grid), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((k_mortar_lift_rd<T, NP, false>), dim3(grid), dim3(256), 0, st, a);
+    if (met) hipLaunchKernelGGL((k_mortar_lift_rd<T, NP, true>), dim3(grid), dim3(64 * rd_lift_waves(NP)), 0, st, a);
+    else hipLaunchKernelGGL((k_mortar_lift_rd<T, NP, false>), dim3(grid), dim3(64 * rd_lift_waves(NP)), 0, st, a);
     return hipGetLastError();
 }
 
@@ -1029,7 +1031,7 @@ static int rd_lift_occ(bool met)
     int nb = 0;
     const void *k = met ? reinterpret_cast<const void *>(&k_mortar_lift_rd<T, NP, true>)
                         : reinterpret_cast<const void *>(&k_mortar_lift_rd<T, NP, false>);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 256, 0) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 64 * rd_lift_waves(NP), 0) != hipSuccess) return 1;
     return nb > 0 ? nb : 1;
 }
 

@@ -685,16 +685,16 @@ int mortar_lifting(mortar_handle *h, const void *const *U_s, const void *const *
     for (size_t i = 0; i < h->ifs.size(); ++i) {
         const Iface &f = h->ifs[i];
         const bool met = f.d_metrics != nullptr, f64 = f.elem == 8;
-        if (!f64 && f.d.N <= 5) {
-            // FP32 up to degree 5: the register-direct body (one wave per 15-face tile);
-            // plane N = 5, 128x64: 18.8 us against 25.6 us for the VALU kernel.  At
-            // degree 7 it holds more registers (two waves per SIMD) and loses (annulus
-            // N = 7, 512x64: 165 us against 143 us); degrees 6 and up keep the VALU
-            // kernel.
+        if (!f64 && f.d.N <= kMaxNFast) {
+            // FP32 up to degree 9: the register-direct body (one wave per 15-face tile;
+            // from NP = 8 in the lockstep rounds of the flux launches).  Plane N = 5,
+            // 128x64: 18.8 us against 25.6 us for the VALU kernel; annulus N = 7, 512x64:
+            // 111.5 us against 145 us (with four free waves instead of the rounds: 165).
             const int tiles_per_row = (f.d.n_par + kRdTileFaces - 1) / kRdTileFaces;
             const int tile_len = (f.d.n_par + tiles_per_row - 1) / tiles_per_row;
             const int n_tiles = tiles_per_row * f.NP * f.d.n_perp;
-            const int grid = std::max(8, std::min((n_tiles + 3) / 4, lift_rd_occupancy_f32(f.NP, met) * h->n_cu));
+            const int w = rd_lift_waves(f.NP);
+            const int grid = std::max(8, std::min((n_tiles + w - 1) / w, lift_rd_occupancy_f32(f.NP, met) * h->n_cu));
             FluxArgs<float> a;
             int nt = 0;
             fill_args(f, U_s[i], U_m[i], nullptr, nullptr, L_s[i], L_m[i], a, nt);

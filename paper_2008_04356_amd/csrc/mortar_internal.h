@@ -173,6 +173,11 @@ __host__ __device__ constexpr int rd_waves(int elem_bytes, bool ns, int np)
 {
     return rd_lockstep(elem_bytes, ns, np) ? kRdLockWaves : 4;
 }
+// The register-direct lifting launches (FP32): lockstep rounds of eight waves from this
+// many nodes per line on (two waves per SIMD there; the rounds write each line's two
+// halves together: annulus N = 7 lifting 165 -> 111.5 us), four free waves below.
+constexpr int kRdLockLiftNP = 8;
+__host__ __device__ constexpr int rd_lift_waves(int np) { return np >= kRdLockLiftNP ? kRdLockWaves : 4; }
 // the batch kernel (4-byte data, both physics)
 constexpr int kRdBatchWaves = kRdLockWaves;
 // Largest array (bytes) the register-direct kernels address with 32-bit buffer offsets;
