@@ -30,6 +30,11 @@
  *                                  scaled to unit length there (on curved interfaces the
  *                                  interpolant of unit normals is shorter between nodes).
  *   The face (i_par, i_perp) of a side is column face_id[i_perp * n_par + i_par].
+ *   Performance: the rows of an array are n_face elements apart; when that stride is a
+ *   multiple of a large power of two, the rows of all (variable, point) planes fall into
+ *   the same cache sets and lines are fetched again.  A face dimension padded by 32
+ *   unused columns (n_face = 32,800 instead of 32,768, plane annular N = 7, FP32)
+ *   removed 15 % of the HBM reads and 8 % of the flux launch time.
  *
  * Ownership: descriptor arrays are host memory owned by the caller and copied during
  * mortar_setup.  Face arrays passed to mortar_flux are device memory owned by the
