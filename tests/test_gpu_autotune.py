@@ -153,6 +153,40 @@ def _close(a, b, rel=1e-6):
     return True
 
 
+@pytest.mark.parametrize("riemann", [W.ROE, W.LF])
+def test_batched_register_direct_kernel_euler(M, riemann):
+    """An Euler batch of degrees 7, 5, 3 (FP32) through the batched register-direct kernel:
+    its N = 7 member runs in the lockstep rounds, the others with the same eight-wave
+    workgroups; every member agrees with its own register-direct launch to a few ulps and
+    with the oracle to the FP32 tolerance, on two grids."""
+    specs = [W.make_plane(7, 41, 3, physics=W.EULER, riemann=riemann, precision=W.FP32,
+                          scramble_seed=5, extra_cols=1, name="e7"),
+             W.make_plane(5, 33, 2, physics=W.EULER, riemann=riemann, precision=W.FP32, name="e5"),
+             W.make_plane(3, 17, 3, physics=W.EULER, riemann=riemann, precision=W.FP32, name="e3")]
+    disp = [2.3 * s.l_par for s in specs]
+    op, dins, oins = _setup(M, specs, disp, seed=11)
+    singles = []
+    try:
+        for i, s in enumerate(specs):
+            o = M.MortarOperator([s])
+            o.update([disp[i]])
+            assert M.mortar_set_tuning(o.h, 0, M.KERNEL_REGISTER, 0, 0) == 0
+            singles.append((o, H.gpu_flux(o, [s], [dins[i]])[0]))
+        for grid in (0, 11):
+            assert M.mortar_set_tuning(op.h, 0, M.KERNEL_REGISTER, 0, grid) == 0
+            outs = H.gpu_flux(op, specs, dins)
+            for i, s in enumerate(specs):
+                assert _close(outs[i][0], singles[i][1][0]) and _close(outs[i][1], singles[i][1][1]), s.name
+                n, sf = O.decompose(disp[i], s.l_par)
+                ref = H.oracle_flux(s, oins[i], n, sf)
+                err = H.rel_err(s, (outs[i][0].cpu().numpy(), outs[i][1].cpu().numpy()), ref)
+                assert np.max(err) <= H.TOL[W.FP32], (s.name, grid, err)
+    finally:
+        for o, _ in singles:
+            o.close()
+        op.close()
+
+
 def test_batched_register_direct_kernel(M):
     """The batched register-direct kernel (FP32, N = 3, 5, 7) agrees with each interface's
     own register-direct launch to a few ulps, and with the oracle to the FP32 tolerance."""
