@@ -56,6 +56,9 @@ def parse():
                         "interface separated by '/'")
     p.add_argument("--copy-calibration", type=float, default=0.0,
                    help="only run a plain device copy of this many MB (counter calibration)")
+    p.add_argument("--stream-reference", type=float, default=0.0,
+                   help="only time torch's device copy, read-only sum and fill of an FP32 "
+                        "array of this many GiB (the rates plain streams reach on this GPU)")
     return p.parse_args()
 
 
@@ -70,6 +73,35 @@ def copy_calibration(mb):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 5}))
+
+
+def stream_reference(gib, reps=20):
+    """HBM rates of plain streams over an FP32 array of `gib` GiB, each the average of
+    `reps` back-to-back launches between two events: a device copy (bytes read plus
+    written), a read-only sum, a fill (bytes written).  Context for the roofline fraction,
+    which is always taken against the published peak."""
+    import torch
+    n = int(gib * (1 << 30)) // 4
+    x = torch.rand(n, device="cuda")
+    y = torch.empty_like(x)
+    s = torch.empty((), device="cuda")
+    legs = {"copy": (lambda: y.copy_(x), 8 * n),
+            "sum": (lambda: torch.sum(x, 0, out=s), 4 * n),
+            "fill": (lambda: y.fill_(2.0), 4 * n)}
+    out = {"array_bytes": 4 * n, "reps": reps}
+    for name, (fn, nbytes) in legs.items():
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) * 1e-3 / reps
+        out[name + "_GBs"] = nbytes / sec / 1e9
+    print(json.dumps(out))
 
 
 TRAFFIC_PROFILES = {2: "profiles/k_mortar_flux_ns_n5_plane128x64_traffic.md",
@@ -453,6 +485,10 @@ def main():
     if a.copy_calibration > 0:
         torch.cuda.set_device(0)
         copy_calibration(a.copy_calibration)
+        return
+    if a.stream_reference > 0:
+        torch.cuda.set_device(0)
+        stream_reference(a.stream_reference)
         return
 
     from paper_2008_04356_amd import mortar as M
