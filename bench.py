@@ -75,21 +75,21 @@ def copy_calibration(mb):
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 5}))
 
 
-def stream_reference(gib, reps=20):
-    """HBM rates of plain streams over an FP32 array of `gib` GiB, each the average of
-    `reps` back-to-back launches between two events: a device copy (bytes read plus
-    written), a read-only sum, a fill (bytes written).  Context for the roofline fraction,
-    which is always taken against the published peak."""
+def stream_rates(gib, legs=("copy", "sum", "fill"), reps=20):
+    """HBM rates (GB/s) of plain streams over an FP32 array of `gib` GiB, each the
+    average of `reps` back-to-back launches between two events: a device copy (bytes
+    read plus written), a read-only sum, a fill (bytes written)."""
     import torch
     n = int(gib * (1 << 30)) // 4
     x = torch.rand(n, device="cuda")
     y = torch.empty_like(x)
     s = torch.empty((), device="cuda")
-    legs = {"copy": (lambda: y.copy_(x), 8 * n),
-            "sum": (lambda: torch.sum(x, 0, out=s), 4 * n),
-            "fill": (lambda: y.fill_(2.0), 4 * n)}
-    out = {"array_bytes": 4 * n, "reps": reps}
-    for name, (fn, nbytes) in legs.items():
+    table = {"copy": (lambda: y.copy_(x), 8 * n),
+             "sum": (lambda: torch.sum(x, 0, out=s), 4 * n),
+             "fill": (lambda: y.fill_(2.0), 4 * n)}
+    out = {}
+    for name in legs:
+        fn, nbytes = table[name]
         for _ in range(3):
             fn()
         torch.cuda.synchronize()
@@ -101,6 +101,16 @@ def stream_reference(gib, reps=20):
         torch.cuda.synchronize()
         sec = e0.elapsed_time(e1) * 1e-3 / reps
         out[name + "_GBs"] = nbytes / sec / 1e9
+    del x, y, s
+    torch.cuda.empty_cache()
+    return out
+
+
+def stream_reference(gib, reps=20):
+    """Context for the roofline fraction, which is always taken against the published
+    peak: the rates plain streams reach on this GPU."""
+    out = {"array_bytes": 4 * (int(gib * (1 << 30)) // 4), "reps": reps}
+    out.update(stream_rates(gib, reps=reps))
     print(json.dumps(out))
 
 
@@ -536,6 +546,9 @@ def main():
                 "polynomial face geometry, per-point metrics, Navier-Stokes Roe+BR1, FP32",
              7: f"conical interface (30 deg) N={spec.N}, {spec.n_par}x{spec.n_perp} face pairs, "
                 "polynomial face geometry, per-point metrics, Navier-Stokes Roe+BR1, FP32"}
+    # a plain device copy timed in the same process after the measured region: the
+    # fraction of what a copy reaches, reported beside the fraction of the published peak
+    copy_gbs = stream_rates(1.0, legs=("copy",))["copy_GBs"]
     out = {
         "metric": "mortar flux points/sec and HBM GB/s vs peak, batched FP32 vs plain FP64",
         "value": r32["pts_per_s"],
@@ -569,7 +582,9 @@ def main():
                      "unit": "GB/s", "frac": r32["frac"],
                      "traffic": measured_traffic(a.config, a.precision, r32["tuning"]),
                      "kernel": kernel,
-                     "bytes_per_launch": r32["bytes_per_launch"]},
+                     "bytes_per_launch": r32["bytes_per_launch"],
+                     "measured_copy_GBs": copy_gbs,
+                     "frac_of_measured_copy": r32["achieved_GBs"] / copy_gbs},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
