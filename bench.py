@@ -549,6 +549,7 @@ def main():
     # a plain device copy timed in the same process after the measured region: the
     # fraction of what a copy reaches, reported beside the fraction of the published peak
     copy_gbs = stream_rates(1.0, legs=("copy",))["copy_GBs"]
+    traffic = measured_traffic(a.config, a.precision, r32["tuning"])
     out = {
         "metric": "mortar flux points/sec and HBM GB/s vs peak, batched FP32 vs plain FP64",
         "value": r32["pts_per_s"],
@@ -580,7 +581,10 @@ def main():
                    "lifting": r32["lifting"]},
         "roofline": {"bound": "hbm", "achieved": r32["achieved_GBs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": r32["frac"],
-                     "traffic": measured_traffic(a.config, a.precision, r32["tuning"]),
+                     "traffic": traffic,
+                     # the counters' bytes over the same average launch duration
+                     "traffic_GBs": None if traffic is None
+                     else traffic / (r32["kernel_ms_avg"] * 1e-3) / 1e9,
                      "kernel": kernel,
                      "bytes_per_launch": r32["bytes_per_launch"],
                      "measured_copy_GBs": copy_gbs,
