@@ -923,7 +923,8 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
     }
 }
 
-// The BR1 lifting surface term through the register-direct body (four free waves).
+// The BR1 lifting surface term through the register-direct body: four free waves per
+// workgroup below NP = 8, the eight-wave lockstep rounds of the flux launches from NP = 8.
 template <typename T, int NP, bool MET>
 __global__ __launch_bounds__(64 * rd_lift_waves(NP)) void k_mortar_lift_rd(FluxArgs<T> a)
 {
