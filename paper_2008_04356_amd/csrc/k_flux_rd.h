@@ -238,20 +238,48 @@ __device__ __forceinline__ float rd_fp16_scale(float m, float &inv)
     return __uint_as_float((uint32_t)(127 - ex) << 23);
 }
 
+// Workgroups of this workgroup's XCD (blockIdx.x % kXcds), and this workgroup's place
+// among them after a rotation by rot (0 <= rot < that count).  A batch rotates the order
+// from one interface to the next (rd_next_rot), so that the workgroups that take the
+// last, partial round of one interface come last in the next one's.
+__device__ __forceinline__ int rd_xcd_workgroups()
+{
+    const int g = gridDim.x, xcd = blockIdx.x % kXcds;
+    return g / kXcds + ((g % kXcds) > xcd ? 1 : 0);
+}
+__device__ __forceinline__ int rd_place(int nwg, int rot) { return (blockIdx.x / kXcds + rot) % nwg; }
+
+// The rotation for the next interface, given that of this one: a share of len tiles
+// taken unit units per workgroup and round leaves its last round to the e workgroups at
+// places 0 .. e-1; the next interface starts its places at the workgroup after them.
+__device__ __forceinline__ int rd_next_rot(int len, int unit, int rot)
+{
+    const int nwg = rd_xcd_workgroups();
+    const int e = ((max(len, 0) % (nwg * unit)) + unit - 1) / unit;   // 0 <= e <= nwg
+    return (rot - e + nwg) % nwg;
+}
+
 // Persistent schedule at wave granularity, with the XCD split of TileCursor: XCD x owns
 // the contiguous eighth of the tiles, and the waves of the workgroups on that XCD take
 // them in turn.  Requires gridDim.x >= min(8, n) so that every XCD's share has workers.
 struct WaveCursor {
     int k, limit, stride;
-    __device__ WaveCursor(int n, int waves, int wave)
+    __device__ WaveCursor(int n, int waves, int wave, int rot = 0)
     {
-        const int g = gridDim.x;
         const int xcd = blockIdx.x % kXcds;
-        stride = (g / kXcds + ((g % kXcds) > xcd ? 1 : 0)) * waves;
+        const int nwg = rd_xcd_workgroups();
+        stride = nwg * waves;
         const int per = (n + kXcds - 1) / kXcds;
         const int base = xcd * per;
         limit = min(n, base + per);
-        k = base + (blockIdx.x / kXcds) * waves + wave;
+        k = base + rd_place(nwg, rot) * waves + wave;
+    }
+    // the rotation for the next interface of a batch
+    static __device__ int next_rot(int n, int waves, int rot)
+    {
+        const int per = (n + kXcds - 1) / kXcds;
+        const int base = (blockIdx.x % kXcds) * per;
+        return rd_next_rot(min(n, base + per) - base, waves, rot);
     }
     __device__ bool valid() const { return k < limit; }
     // some wave of this workgroup has a tile in the current round (the same answer for
@@ -269,22 +297,30 @@ struct WaveCursor {
 // wave of the workgroup.
 struct HalfCursor {
     int k, limit, stride, first, first_limit;
-    __device__ HalfCursor(int n, int waves, int wave)
+    __device__ HalfCursor(int n, int waves, int wave, int rot = 0)
     {
-        const int g = gridDim.x;
         const int xcd = blockIdx.x % kXcds;
-        const int nwg = g / kXcds + ((g % kXcds) > xcd ? 1 : 0);
+        const int nwg = rd_xcd_workgroups();
         const int per = (n + kXcds - 1) / kXcds;
         const int base = min(n, xcd * per);
         const int lim = min(n, base + per);
         const int mid = base + (lim - base + 1) / 2;
         const int hw = waves / 2;
         const int grp = wave < hw ? 0 : 1;
+        const int place = rd_place(nwg, rot);
         stride = nwg * hw;
-        first = base + (blockIdx.x / kXcds) * hw;
+        first = base + place * hw;
         first_limit = mid;
-        k = (grp ? mid : base) + (blockIdx.x / kXcds) * hw + (wave - grp * hw);
+        k = (grp ? mid : base) + place * hw + (wave - grp * hw);
         limit = grp ? lim : mid;
+    }
+    // the rotation for the next interface of a batch: the rounds follow the first half
+    static __device__ int next_rot(int n, int waves, int rot)
+    {
+        const int per = (n + kXcds - 1) / kXcds;
+        const int base = min(n, (blockIdx.x % kXcds) * per);
+        const int lim = min(n, base + per);
+        return rd_next_rot((lim - base + 1) / 2, waves / 2, rot);
     }
     __device__ bool valid() const { return k < limit; }
     __device__ bool round_valid(int) const { return first < first_limit; }
@@ -309,8 +345,8 @@ struct HalfCursor {
 // each component of the static unit normal and the surface element, 15 values
 // (component d, variable v at plane 5 d + v) back-projected onto both sides.
 template <typename T, int NP, bool NSV, bool MET, int RIEM, int PREC, int WV, bool LIFT = false>
-__device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work, T *mats, double *wq,
-                                             double *acc, double *red)
+__device__ __forceinline__ int rd_interface(const FluxArgs<T> &a, double *work, T *mats, double *wq,
+                                            double *acc, double *red, int rot = 0)
 {
     static_assert(!LIFT || (!NSV && PREC == 0), "lifting: states only, element-type products");
     constexpr int NOUT = LIFT ? 15 : 5;      // output planes per side
@@ -597,7 +633,7 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
     // launches keep three or four waves per SIMD in four-wave workgroups).
     constexpr bool LOCKSTEP = LIFT ? WV == kRdLockWaves : rd_lockstep((int)sizeof(T), NSV, NP);
     using Cursor = std::conditional_t<LOCKSTEP && kRdPingPong && kRdSplitHalves, HalfCursor, WaveCursor>;
-    Cursor cur(a.n_tiles, C::WAVES, wave);
+    Cursor cur(a.n_tiles, C::WAVES, wave, rot);
     bool more = LOCKSTEP ? cur.round_valid(wave) : cur.valid();
     bool mine = cur.valid();
     TileGeom g = tile_geom(a, mine ? cur.tile() : 0, NP);
@@ -921,6 +957,7 @@ __device__ __forceinline__ void rd_interface(const FluxArgs<T> &a, double *work,
         }
         __syncthreads();
     }
+    return Cursor::next_rot(a.n_tiles, C::WAVES, rot);
 }
 
 // The BR1 lifting surface term through the register-direct body: four free waves per
@@ -952,8 +989,10 @@ __global__ __launch_bounds__(64 * rd_waves((int)sizeof(T), NSV, NP)) void k_mort
 
 // Every interface of a batch in one persistent launch (degrees N = 3, 5, 7, element type
 // FP32): the workgroups take the interfaces one after the other, each with its own
-// XCD-aware wave cursor.  The bodies are inlined; the host launches this kernel only
-// for batches whose degrees are all in {3, 5, 7}.
+// XCD-aware wave cursor.  Each interface starts the order of its workgroups after those
+// that took the previous interface's last, partial round, so that no workgroup takes
+// the partial round of every interface.  The bodies are inlined; the host launches this
+// kernel only for batches whose degrees are all in {3, 5, 7}.
 template <bool NSV, int RIEM>
 __global__ __launch_bounds__(64 * kRdBatchWaves) __attribute__((amdgpu_waves_per_eu(2))) void k_mortar_flux_rd_batch(BatchArgs<float> b)
 {
@@ -964,12 +1003,13 @@ __global__ __launch_bounds__(64 * kRdBatchWaves) __attribute__((amdgpu_waves_per
     __shared__ double wq[NPM];
     __shared__ double acc[20 * NT];
     __shared__ double red[320];
+    int rot = 0;
     for (int i = 0; i < b.n_if; ++i) {
         const bool met = b.met[i] != 0;
 #define MORTAR_RD_BATCH_NP(NPV)                                                               \
     if (b.np[i] == NPV) {                                                                     \
-        if (met) rd_interface<float, NPV, NSV, true, RIEM, 0, kRdBatchWaves>(b.a[i], work, mats, wq, acc, red); \
-        else rd_interface<float, NPV, NSV, false, RIEM, 0, kRdBatchWaves>(b.a[i], work, mats, wq, acc, red);    \
+        rot = met ? rd_interface<float, NPV, NSV, true, RIEM, 0, kRdBatchWaves>(b.a[i], work, mats, wq, acc, red, rot) \
+                  : rd_interface<float, NPV, NSV, false, RIEM, 0, kRdBatchWaves>(b.a[i], work, mats, wq, acc, red, rot); \
         continue;                                                                             \
     }
         MORTAR_RD_BATCH_NP(4) MORTAR_RD_BATCH_NP(6) MORTAR_RD_BATCH_NP(8)
