@@ -248,14 +248,15 @@ def run_leg(M, W, specs, disp, steps, warmup, rotate_bytes, graph=False, plain=F
         torch.cuda.synchronize()
         print(f"[bench] autotune {time.time() - t1:.2f} s: {tuning}", file=sys.stderr, flush=True)
 
-    graphs = None
-    if graph:
-        ops[0].update(disp(0))
-        graphs = [ops[0].graph(*args(per)) for per in sets]
-
     # per-stage conservation residual sums (FP64, on the device, no synchronization)
     cons_dev = [torch.zeros((1 if plain else len(specs), 5, 3), dtype=torch.float64, device="cuda")
                 for _ in ops]
+
+    # graph mode: one captured stage per buffer set, flux and conservation sums together
+    graphs = None
+    if graph:
+        ops[0].update(disp(0))
+        graphs = [ops[0].graph(*args(per), cons_out=cons_dev[0]) for per in sets]
 
     # eager stages with their arguments marshalled once per buffer set (update + flux +
     # conservation sums: three C calls per operator)
@@ -265,10 +266,7 @@ def run_leg(M, W, specs, disp, steps, warmup, rotate_bytes, graph=False, plain=F
     def step(k):
         d = disp(k)
         if graph:
-            per = sets[k % nsets]
             graphs[k % nsets].launch(d)
-            op = ops[0]
-            op.conservation_device([p["Fs"] for p in per], [p["Fm"] for p in per], cons_dev[0])
         else:
             for i, st in enumerate(stages[k % nsets]):
                 st([d[i]] if plain else d)

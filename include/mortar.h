@@ -167,6 +167,18 @@ int mortar_graph_create(mortar_handle *h, const void *const *U_s, const void *co
 int mortar_graph_launch(mortar_graph *g, const double *disp, void *stream);
 int mortar_graph_destroy(mortar_graph *g);
 
+/* mortar_graph_create_cons: mortar_graph_create with the stage's conservation sums
+ * (Sec. 3.2: both sides' integrals of the projected flux) in the same graph.  After the
+ * flux launch(es) the graph computes what mortar_conservation_device(h, F_s, F_m, d_cons)
+ * computes for those outputs, into d_cons ([n_iface][5][3] doubles in device memory,
+ * owned by the caller and kept valid for the graph's lifetime).  mortar_graph_launch
+ * then runs a whole stage (update, flux, conservation sums) with no host launch between
+ * the flux and the sums.  d_cons NULL: INVALID_ARG; otherwise errors as for
+ * mortar_graph_create. */
+int mortar_graph_create_cons(mortar_handle *h, const void *const *U_s, const void *const *U_m,
+                             const void *const *G_s, const void *const *G_m, void *const *F_s,
+                             void *const *F_m, double *d_cons, mortar_graph **out);
+
 /* ---- launch tuning ----------------------------------------------------------------
  * How an interface's flux is launched.  variant: MORTAR_KERNEL_VALU (projections on the
  * vector units, tiles staged in LDS), MORTAR_KERNEL_MFMA_LDS (projections as matrix-core

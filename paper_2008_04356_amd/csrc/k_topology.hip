@@ -375,6 +375,16 @@ hipError_t launch_conservation_final_batch(const Iface *const *fs, double *const
     return hipGetLastError();
 }
 
+// Whether a kernel (its host handle, as a graph's kernel node records it) is one of the
+// conservation kernels, so that a captured stage can tell its flux nodes from them.
+bool is_conservation_kernel(const void *func)
+{
+    return func == reinterpret_cast<const void *>(&k_cons_final) ||
+           func == reinterpret_cast<const void *>(&k_cons_final_batch) ||
+           func == reinterpret_cast<const void *>(&k_cons_partial<float>) ||
+           func == reinterpret_cast<const void *>(&k_cons_partial<double>);
+}
+
 // Sums from the partials a fused flux launch wrote (one per workgroup and group).
 hipError_t launch_conservation_final(const Iface &f, double *d_out, hipStream_t st)
 {

@@ -50,6 +50,8 @@ int flux_rd_batch_occupancy_f32(bool ns, int riem);
 hipError_t launch_flux_rd_batch_f32(const BatchArgs<float> &b, int grid, bool ns, int riem,
                                     hipStream_t st);
 int flux_rd_occupancy_f32(int NP, bool ns, bool met, int riem);
+// the conservation kernels' host handles (k_topology.hip)
+bool is_conservation_kernel(const void *func);
 int flux_rd_occupancy_f64(int NP, bool ns, bool met, int riem);
 int flux_rd_occupancy_bf16(int NP, bool ns, bool met, int riem);
 
@@ -498,13 +500,14 @@ using namespace mortar;
 
 struct mortar_handle : public mortar::Handle {};
 
-// A captured stage: the flux launch(es) of a handle for fixed buffers.
+// A captured stage: the flux launch(es) of a handle for fixed buffers (and, from
+// mortar_graph_create_cons, the stage's conservation sums).
 struct mortar_graph {
     mortar_handle *h = nullptr;
     unsigned epoch = 0;                      // tuning epoch of the handle at capture
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    std::vector<hipGraphNode_t> nodes;       // kernel nodes in launch order
+    std::vector<hipGraphNode_t> nodes;       // flux kernel nodes in launch order
     std::vector<const void *> Us, Um, Gs, Gm;
     std::vector<void *> Fs, Fm;
 };
@@ -834,9 +837,11 @@ int mortar_conservation(mortar_handle *h, const void *const *F_s, const void *co
     return MORTAR_OK;
 }
 
-int mortar_graph_create(mortar_handle *h, const void *const *U_s, const void *const *U_m,
+// The capture behind mortar_graph_create and mortar_graph_create_cons (d_cons non-null:
+// the stage's conservation sums into d_cons after the flux launches).
+static int graph_create(mortar_handle *h, const void *const *U_s, const void *const *U_m,
                         const void *const *G_s, const void *const *G_m, void *const *F_s,
-                        void *const *F_m, mortar_graph **out)
+                        void *const *F_m, double *d_cons, mortar_graph **out)
 {
     if (!h || !out || !U_s || !U_m || !F_s || !F_m) return MORTAR_ERR_INVALID_ARG;
     const size_t n_if = h->ifs.size();
@@ -858,8 +863,10 @@ int mortar_graph_create(mortar_handle *h, const void *const *U_s, const void *co
     if (rc == MORTAR_OK && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess)
         rc = MORTAR_ERR_HIP;
     if (rc == MORTAR_OK) {
-        const int frc = mortar_flux(h, g->Us.data(), g->Um.data(), g->Gs.data(), g->Gm.data(),
-                                    g->Fs.data(), g->Fm.data(), cs);
+        int frc = mortar_flux(h, g->Us.data(), g->Um.data(), g->Gs.data(), g->Gm.data(),
+                              g->Fs.data(), g->Fm.data(), cs);
+        if (frc == MORTAR_OK && d_cons)
+            frc = mortar_conservation_device(h, g->Fs.data(), g->Fm.data(), d_cons, cs);
         hipGraph_t graph = nullptr;
         const hipError_t e = hipStreamEndCapture(cs, &graph);
         g->graph = graph;
@@ -872,13 +879,25 @@ int mortar_graph_create(mortar_handle *h, const void *const *U_s, const void *co
         std::vector<hipGraphNode_t> all(nn);
         if (rc == MORTAR_OK && nn && hipGraphGetNodes(g->graph, all.data(), &nn) != hipSuccess)
             rc = MORTAR_ERR_HIP;
+        // the flux nodes (updated per replay) and the conservation nodes (fixed); no
+        // memset node may be part of a replayed graph
+        size_t n_cons = 0;
         for (size_t i = 0; rc == MORTAR_OK && i < nn; ++i) {
             hipGraphNodeType t;
-            if (hipGraphNodeGetType(all[i], &t) != hipSuccess) rc = MORTAR_ERR_HIP;
-            else if (t == hipGraphNodeTypeKernel) g->nodes.push_back(all[i]);
+            if (hipGraphNodeGetType(all[i], &t) != hipSuccess) {
+                rc = MORTAR_ERR_HIP;
+            } else if (t == hipGraphNodeTypeMemset) {
+                rc = MORTAR_ERR_UNSUPPORTED;
+            } else if (t == hipGraphNodeTypeKernel) {
+                hipKernelNodeParams p{};
+                if (hipGraphKernelNodeGetParams(all[i], &p) != hipSuccess) rc = MORTAR_ERR_HIP;
+                else if (is_conservation_kernel(p.func)) ++n_cons;
+                else g->nodes.push_back(all[i]);
+            }
         }
         const size_t want = h->batched ? 1 : n_if;
         if (rc == MORTAR_OK && g->nodes.size() != want) rc = MORTAR_ERR_UNSUPPORTED;
+        if (rc == MORTAR_OK && (d_cons ? n_cons == 0 : n_cons != 0)) rc = MORTAR_ERR_UNSUPPORTED;
     }
     if (rc == MORTAR_OK && hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess)
         rc = MORTAR_ERR_HIP;
@@ -892,6 +911,21 @@ int mortar_graph_create(mortar_handle *h, const void *const *U_s, const void *co
     }
     *out = g;
     return MORTAR_OK;
+}
+
+int mortar_graph_create(mortar_handle *h, const void *const *U_s, const void *const *U_m,
+                        const void *const *G_s, const void *const *G_m, void *const *F_s,
+                        void *const *F_m, mortar_graph **out)
+{
+    return graph_create(h, U_s, U_m, G_s, G_m, F_s, F_m, nullptr, out);
+}
+
+int mortar_graph_create_cons(mortar_handle *h, const void *const *U_s, const void *const *U_m,
+                             const void *const *G_s, const void *const *G_m, void *const *F_s,
+                             void *const *F_m, double *d_cons, mortar_graph **out)
+{
+    if (!d_cons) return MORTAR_ERR_INVALID_ARG;
+    return graph_create(h, U_s, U_m, G_s, G_m, F_s, F_m, d_cons, out);
 }
 
 }  // extern "C"

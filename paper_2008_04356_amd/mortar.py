@@ -79,6 +79,8 @@ def _load():
     L.mortar_conservation_device_noalloc.argtypes = [C.c_void_p, _vpp, _vpp, C.c_void_p, C.c_void_p]
     L.mortar_graph_create.argtypes = [C.c_void_p, _vpp, _vpp, _vpp, _vpp, _vpp, _vpp,
                                       C.POINTER(C.c_void_p)]
+    L.mortar_graph_create_cons.argtypes = [C.c_void_p, _vpp, _vpp, _vpp, _vpp, _vpp, _vpp,
+                                           C.c_void_p, C.POINTER(C.c_void_p)]
     L.mortar_graph_launch.argtypes = [C.c_void_p, _dp, C.c_void_p]
     L.mortar_graph_destroy.argtypes = [C.c_void_p]
     L.mortar_autotune.argtypes = [C.c_void_p, _vpp, _vpp, _vpp, _vpp, _vpp, _vpp, C.c_int,
@@ -142,6 +144,14 @@ def mortar_graph_create(h, Us, Um, Gs, Gm, Fs, Fm):
     g = C.c_void_p()
     _check(lib.mortar_graph_create(h, _ptrs(Us), _ptrs(Um), _ptrs(Gs), _ptrs(Gm), _ptrs(Fs),
                                    _ptrs(Fm), C.byref(g)), "mortar_graph_create")
+    return g
+
+
+def mortar_graph_create_cons(h, Us, Um, Gs, Gm, Fs, Fm, d_cons: int):
+    g = C.c_void_p()
+    _check(lib.mortar_graph_create_cons(h, _ptrs(Us), _ptrs(Um), _ptrs(Gs), _ptrs(Gm), _ptrs(Fs),
+                                        _ptrs(Fm), C.c_void_p(d_cons), C.byref(g)),
+           "mortar_graph_create_cons")
     return g
 
 
@@ -438,9 +448,11 @@ class MortarOperator:
                                          Pb.ctypes.data_as(_dp)), "mortar_get_projection")
         return Pf, Pb
 
-    def graph(self, Us, Um, Gs, Gm, Fs, Fm):
-        """Captures one stage for these fixed buffers; see MortarGraph."""
-        return MortarGraph(self, Us, Um, Gs, Gm, Fs, Fm)
+    def graph(self, Us, Um, Gs, Gm, Fs, Fm, cons_out=None):
+        """Captures one stage for these fixed buffers; see MortarGraph.  cons_out (a
+        contiguous CUDA float64 tensor [n_iface][5][3]) puts the stage's conservation
+        sums into the same graph."""
+        return MortarGraph(self, Us, Um, Gs, Gm, Fs, Fm, cons_out)
 
     def _check_cons(self, Fs, Fm, out=None):
         import torch
@@ -513,14 +525,21 @@ class MortarStage:
 
 class MortarGraph:
     """One stage of an operator captured as a HIP graph for fixed face buffers; each
-    launch(disp) updates the displacement and replays the graph."""
+    launch(disp) updates the displacement and replays the graph (with cons_out, the
+    graph also writes the stage's conservation sums there)."""
 
-    def __init__(self, op, Us, Um, Gs, Gm, Fs, Fm):
+    def __init__(self, op, Us, Um, Gs, Gm, Fs, Fm, cons_out=None):
         _check_flux_args(op.specs, Us, Um, Gs, Gm, Fs, Fm)
         p = lambda ts: None if ts is None else [None if t is None else t.data_ptr() for t in ts]  # noqa: E731
         self.op = op
-        self._keep = (Us, Um, Gs, Gm, Fs, Fm)
-        self.g = mortar_graph_create(op.h, p(Us), p(Um), p(Gs), p(Gm), p(Fs), p(Fm))
+        self._keep = (Us, Um, Gs, Gm, Fs, Fm, cons_out)
+        self.g = None
+        if cons_out is None:
+            self.g = mortar_graph_create(op.h, p(Us), p(Um), p(Gs), p(Gm), p(Fs), p(Fm))
+        else:
+            op._check_cons(Fs, Fm, cons_out)
+            self.g = mortar_graph_create_cons(op.h, p(Us), p(Um), p(Gs), p(Gm), p(Fs), p(Fm),
+                                              cons_out.data_ptr())
 
     def launch(self, disp, stream=None):
         _check_disp(disp, self.op.specs, "mortar_graph_launch")

@@ -157,3 +157,65 @@ def test_graph_replay_conservation_from_fused_partials(M):
             graph.close()
     finally:
         op.close()
+
+
+@pytest.mark.parametrize("which", ["fp32_batch", "fp64_single"])
+def test_graph_with_conservation_sums(M, which):
+    """A stage graph holding the conservation sums (mortar_graph_create_cons): after every
+    replay the sums it wrote equal, bit for bit, those an eager conservation_device call
+    forms from the same flux outputs, and agree with a pass over copies of them; the
+    program's own eager work runs between the replays."""
+    import torch
+    if which == "fp32_batch":
+        specs = _turbine_like(W.FP32)
+    else:
+        specs = [W.make_plane(5, 53, 3, physics=W.NS, riemann=W.ROE, mu=1e-3, precision=W.FP64,
+                              scramble_seed=7, name="g64")]
+    ins = [W.make_inputs(s, seed=40 + i, noise=1e-3) for i, s in enumerate(specs)]
+    dins = [H.device_inputs(s, x) for s, x in zip(specs, ins)]
+    op = M.MortarOperator(specs)
+    try:
+        outs = [H.alloc_outputs(s) for s in specs]
+        cons_g = torch.zeros((len(specs), 5, 3), dtype=torch.float64, device="cuda:0")
+        op.update([0.0] * len(specs))
+        graph = op.graph([d["Us"] for d in dins], [d["Um"] for d in dins],
+                         [d["Gs"] for d in dins], [d["Gm"] for d in dins],
+                         [o[0] for o in outs], [o[1] for o in outs], cons_out=cons_g)
+        try:
+            for k in range(6):
+                # steps of several faces, so that some stages rebuild the index maps
+                disp = [(0.37 + 5.3 * k) * s.l_par for s in specs]
+                print(f"[graph+cons] {which} stage {k}", flush=True)
+                graph.launch(disp)
+                torch.cuda.synchronize()
+                got = cons_g.cpu().numpy().copy()
+                ref = torch.zeros_like(cons_g)
+                op.conservation_device([o[0] for o in outs], [o[1] for o in outs], ref)
+                scratch = torch.randn(1 << 20, device="cuda").sum()   # eager work between replays
+                torch.cuda.synchronize()
+                del scratch
+                assert np.array_equal(got, ref.cpu().numpy()), (k, got, ref)
+                passed = np.array(op.conservation([o[0].clone() for o in outs],
+                                                  [o[1].clone() for o in outs]))
+                assert np.all(np.abs(got - passed) <= 1e-13 * passed[:, :, 2:3] + 1e-300), (k, got, passed)
+                assert np.all(passed[:, :, 2] > 0)
+        finally:
+            graph.close()
+    finally:
+        op.close()
+
+
+def test_graph_with_conservation_rejects_missing_output(M):
+    specs = _turbine_like(W.FP32)
+    dins = [H.device_inputs(s, W.make_inputs(s, seed=50 + i, noise=1e-3)) for i, s in enumerate(specs)]
+    op = M.MortarOperator(specs)
+    try:
+        outs = [H.alloc_outputs(s) for s in specs]
+        op.update([0.0] * len(specs))
+        p = lambda ts: [t.data_ptr() for t in ts]  # noqa: E731
+        with pytest.raises(M.MortarError):
+            M.mortar_graph_create_cons(op.h, p([d["Us"] for d in dins]), p([d["Um"] for d in dins]),
+                                       p([d["Gs"] for d in dins]), p([d["Gm"] for d in dins]),
+                                       p([o[0] for o in outs]), p([o[1] for o in outs]), 0)
+    finally:
+        op.close()
