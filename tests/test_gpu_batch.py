@@ -159,7 +159,7 @@ def test_graph_replay_conservation_from_fused_partials(M):
         op.close()
 
 
-@pytest.mark.parametrize("which", ["fp32_batch", "fp64_single"])
+@pytest.mark.parametrize("which", ["fp32_batch", "fp64_single", "mixed"])
 def test_graph_with_conservation_sums(M, which):
     """A stage graph holding the conservation sums (mortar_graph_create_cons): after every
     replay the sums it wrote equal, bit for bit, those an eager conservation_device call
@@ -168,9 +168,14 @@ def test_graph_with_conservation_sums(M, which):
     import torch
     if which == "fp32_batch":
         specs = _turbine_like(W.FP32)
-    else:
+    elif which == "fp64_single":
         specs = [W.make_plane(5, 53, 3, physics=W.NS, riemann=W.ROE, mu=1e-3, precision=W.FP64,
                               scramble_seed=7, name="g64")]
+    else:
+        # element types differ: one launch per interface, each with its own sums
+        specs = [W.make_plane(3, 20, 2, physics=W.EULER, riemann=W.LF, precision=W.FP64, name="m64"),
+                 W.make_plane(4, 18, 2, physics=W.NS, riemann=W.ROE, mu=1e-3, precision=W.FP32,
+                              name="m32")]
     ins = [W.make_inputs(s, seed=40 + i, noise=1e-3) for i, s in enumerate(specs)]
     dins = [H.device_inputs(s, x) for s, x in zip(specs, ins)]
     op = M.MortarOperator(specs)
