@@ -939,14 +939,17 @@ __device__ __forceinline__ int rd_interface(const FluxArgs<T> &a, double *work, 
     }
     if constexpr (FUSE) {
         // the workgroup's partials: 16 chunks of NT / 16 lanes per slot, then the chunks,
-        // in fixed orders; partial g = 2 v + side at a.cons[(g * gridDim.x + block) * 2 + m]
+        // in fixed orders; partial g = 2 v + side at a.cons[(g * gridDim.x + block) * 2 + m].
+        // Chunk c of a slot holds lanes c, c + 16, c + 32, ..: the chunks of a slot read 16
+        // consecutive doubles at a time (with a contiguous run of lanes per chunk, every
+        // lane of a wave read the same LDS bank pair)
         constexpr int CH = C::NT / 16;
         __syncthreads();
         for (int t = tid; t < 320; t += C::NT) {
             const int k = t >> 4, c = t & 15;
-            const double *q = acc + k * C::NT + c * CH;
+            const double *q = acc + k * C::NT + c;
             double x = 0.0;
-            for (int l = 0; l < CH; ++l) x += q[l];
+            for (int l = 0; l < CH; ++l) x += q[16 * l];
             red[t] = x;
         }
         __syncthreads();
