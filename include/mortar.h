@@ -173,7 +173,9 @@ int mortar_graph_destroy(mortar_graph *g);
  * computes for those outputs, into d_cons ([n_iface][5][3] doubles in device memory,
  * owned by the caller and kept valid for the graph's lifetime).  mortar_graph_launch
  * then runs a whole stage (update, flux, conservation sums) with no host launch between
- * the flux and the sums.  d_cons NULL: INVALID_ARG; otherwise errors as for
+ * the flux and the sums.  Like mortar_conservation_device, the captured sums use the
+ * handle's own partial-sum buffers: other calls of the handle on another stream that
+ * overlap a replay race on them.  d_cons NULL: INVALID_ARG; otherwise errors as for
  * mortar_graph_create. */
 int mortar_graph_create_cons(mortar_handle *h, const void *const *U_s, const void *const *U_m,
                              const void *const *G_s, const void *const *G_m, void *const *F_s,
